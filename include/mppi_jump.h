@@ -1,0 +1,229 @@
+/*
+ * mppi_jump.h - C ABI of the MI355X (gfx950) library for one iteration of
+ * model predictive path-integral control on a jump-diffusion process
+ * (Wang, Williams, Theodorou, "Information Theoretic Model Predictive
+ * Control on Jump Diffusion Processes", arXiv 1807.06108).
+ *
+ * One iteration (Algorithm 1 of the paper) is:
+ *   1. sample K perturbed control sequences: Gaussian noise plus
+ *      compound-Poisson jumps (Sec. IV-B noise model, Algorithm 1 jump timer);
+ *   2. roll out the K trajectories of the dynamics in parallel with explicit
+ *      Euler steps and accumulate the modified path costs S~_k (eqs. (34)-(35));
+ *   3. weights w_k = exp(-(S~_k - min S~)/lambda) / sum (eq. (37));
+ *   4. U += alpha * sum_k w_k eps_k (eq. (36); step alpha of eq. (49)).
+ * Between control steps the sequence is shifted: u_0 is executed, U moves one
+ * step left and u_init is appended (Algorithm 1, Sec. V).
+ *
+ * Conventions shared by every entry point
+ *   - All device pointers are plain device addresses (or, where stated,
+ *     pinned host addresses that the device can access).  The caller owns
+ *     all device memory; the library never allocates device memory and never
+ *     synchronises a stream, except where an entry point says so.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every entry point that takes a stream only enqueues work on it.
+ *   - Every function returns an int status (MPPI_OK or a negative code); no
+ *     C++ exception crosses this interface and the library never aborts.
+ *     mppi_jump_last_error() gives a human-readable detail for the calling
+ *     thread's last failure.
+ *   - A context is not thread-safe; distinct contexts on distinct streams are
+ *     independent.
+ */
+#ifndef MPPI_JUMP_H
+#define MPPI_JUMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPPI_JUMP_ABI_VERSION 1
+
+#define MPPI_JUMP_MAX_N 12      /* state dimension bound            */
+#define MPPI_JUMP_MAX_M 4       /* control dimension bound          */
+#define MPPI_JUMP_MAX_Q 3       /* jump-mark dimension bound        */
+#define MPPI_JUMP_MAX_LEVELS 32 /* count-law inversion levels       */
+#define MPPI_JUMP_MAX_K (1 << 24)
+#define MPPI_JUMP_MAX_T 4096
+
+/* status codes */
+#define MPPI_OK 0
+#define MPPI_EINVAL -1        /* invalid argument or configuration          */
+#define MPPI_EWORKSPACE -2    /* workspace too small or misaligned          */
+#define MPPI_EDEVICE -3       /* a HIP runtime call failed                  */
+#define MPPI_ENONFINITE -4    /* every S~_k was non-finite; U left unchanged */
+#define MPPI_EUNSUPPORTED -5  /* valid request this build does not support  */
+
+/* dynamics ids: (n, m, q) = state, control and jump-mark dimensions */
+#define MPPI_DYN_LINEAR 0     /* double integrator, (2, 1, 1)  */
+#define MPPI_DYN_CARTPOLE 1   /* cartpole, (4, 1, 1)           */
+#define MPPI_DYN_QUADROTOR 2  /* 12-state quadrotor, (12, 4, 3) */
+
+/* jump count law (Sec. IV-B): Poisson(nu dt) or the zero-one law */
+#define MPPI_COUNT_POISSON 0
+#define MPPI_COUNT_ZERO_ONE 1
+
+/* path-cost form: information-theoretic (eqs. (34)-(35), with the
+ * importance-sampling terms) or stochastic-optimisation (Sec. IV: cost on the
+ * applied control, no importance-sampling term) */
+#define MPPI_COST_IT 0
+#define MPPI_COST_SO 1
+
+/* items of mppi_jump_get / mppi_jump_set */
+#define MPPI_ITEM_U 0        /* float [T][m]                        get, set */
+#define MPPI_ITEM_S 1        /* double [K] path costs S~_k          get, set */
+#define MPPI_ITEM_W 2        /* double [K] normalised weights       get      */
+#define MPPI_ITEM_STATS 3    /* mppi_jump_stats                     get      */
+#define MPPI_ITEM_EPS 4      /* float [T][m][K] perturbations       get      */
+#define MPPI_ITEM_DBG_ZD 5   /* float [K][T][m] standard normals z_D  (debug_dump) */
+#define MPPI_ITEM_DBG_N 6    /* int32 [K][T] jump counts              (debug_dump) */
+#define MPPI_ITEM_DBG_ZJ 7   /* float [K][T][q] standard normals z_J  (debug_dump) */
+#define MPPI_ITEM_THRESH 8   /* uint64 [MPPI_JUMP_MAX_LEVELS] count thresholds; unused = 2^32 */
+
+/*
+ * Configuration: the "Given" block of Algorithm 1.  All floats are fp32.
+ * Noise parameters are per-step control-space values: the sampled control is
+ * U[t] + eps[k][t] with eps = sigma * z_D (+ a control-channel jump).
+ */
+typedef struct mppi_jump_config {
+  int32_t abi_version;   /* must equal MPPI_JUMP_ABI_VERSION                   */
+  int32_t dynamics;      /* MPPI_DYN_*                                         */
+  int32_t K;             /* samples per iteration, 1..MPPI_JUMP_MAX_K          */
+  int32_t T;             /* horizon steps, 1..MPPI_JUMP_MAX_T                  */
+  float dt;              /* step length (s), > 0                               */
+  float lambda;          /* temperature, > 0                                   */
+  float alpha;           /* update step size (eq. (49)); 1 = Algorithm 1       */
+  float c;               /* importance-sampling variance factor (eq. (35)), >0 */
+  float nu;              /* jump rate (1/s), >= 0; count mean is nu*dt         */
+  int32_t count_law;     /* MPPI_COUNT_*                                       */
+  int32_t cost_form;     /* MPPI_COST_*                                        */
+  int32_t debug_dump;    /* 1: also write z_D, N, z_J for every (k, t)         */
+  float sigma[4];        /* Gaussian std per control channel, >= 0             */
+  float sigma_J[4];      /* jump-mark std per mark channel, >= 0               */
+  float u_init[4];       /* value appended by the shift                         */
+  float R[4];            /* diagonal control cost (eq. (3))                    */
+  float Q[12];           /* diagonal running state cost                        */
+  float Qf[12];          /* diagonal terminal state cost                       */
+  float x_goal[12];      /* target state x*                                    */
+  float params[12];      /* dynamics constants (see below)                     */
+  float crash_penalty;   /* quadrotor crash indicator weight                   */
+  int32_t reserved;      /* must be 0                                          */
+  uint64_t seed;         /* Philox key                                         */
+  uint64_t controller_id;/* < 2^24; part of the Philox counter                 */
+  uint64_t start_iteration; /* iteration index of the first step, < 2^32      */
+} mppi_jump_config;
+/* params: cartpole  = {m_cart, m_pole, half_length, g}
+ *         quadrotor = {mass, Jx, Jy, Jz, arm, k_yaw, g, tilt_max, z_min}
+ *         linear    = unused                                                 */
+
+typedef struct mppi_jump_stats {
+  double rho;            /* min over finite S~_k                              */
+  double eta;            /* sum_k exp(-(S~_k - rho)/lambda)                   */
+  int32_t status;        /* MPPI_OK or MPPI_ENONFINITE of the last iteration  */
+  int32_t n_finite;      /* number of finite S~_k                             */
+  uint64_t iteration;    /* index of the next iteration                       */
+} mppi_jump_stats;
+
+typedef struct mppi_jump_ctx mppi_jump_ctx;
+
+/* ABI version of the loaded library (MPPI_JUMP_ABI_VERSION). */
+int mppi_jump_abi_version(void);
+
+/* State, control and jump-mark dimensions of a dynamics id.
+ * Pure host function.  EINVAL for an unknown id or NULL output. */
+int mppi_jump_dims(int32_t dynamics, int32_t* n, int32_t* m, int32_t* q);
+
+/* Device workspace a configuration needs (perturbations [T][m][K],
+ * costs [K], reduction partials, statistics, control sequence, optional debug
+ * dumps), in bytes, for a 256-byte aligned base.  Pure host function: it
+ * validates the configuration and returns EINVAL for any invalid field. */
+int mppi_jump_workspace_bytes(const mppi_jump_config* cfg, size_t* bytes);
+
+/* Jump-count inversion table of a configuration (Sec. IV-B count law with
+ * mean nu*dt): out[0..MPPI_JUMP_MAX_LEVELS) receives theta_j = floor(F(j) 2^32)
+ * with F the CDF of the count law; entries from the closing level on are
+ * 2^32.  The count drawn from a 32-bit word w is the number of j with
+ * w >= theta_j.  Pure host function; EINVAL for an invalid configuration. */
+int mppi_jump_count_thresholds(const mppi_jump_config* cfg, uint64_t* out);
+
+/* Validate cfg, lay the caller's workspace out and enqueue its
+ * initialisation on `stream`: U <- d_U0 ([T][m] fp32, read during this
+ * enqueue's execution; NULL = u_init at every step), iteration counter <-
+ * start_iteration.  Allocates only the host-side context (*out).
+ * EWORKSPACE if ws_bytes is below mppi_jump_workspace_bytes or d_workspace
+ * is not 256-byte aligned. */
+int mppi_jump_init(const mppi_jump_config* cfg, void* d_workspace, size_t ws_bytes,
+                   const float* d_U0, void* stream, mppi_jump_ctx** out);
+
+/* Enqueue `iters` >= 1 iterations (Algorithm 1, sampling to update) from
+ * the state d_x0 ([n] fp32 device), updating U in place.  Each iteration
+ * draws fresh noise (its own iteration index).  If every S~_k of an
+ * iteration is non-finite, that iteration leaves U unchanged and records
+ * MPPI_ENONFINITE in the statistics (read with MPPI_ITEM_STATS). */
+int mppi_jump_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, void* stream);
+
+/* The two halves of one iteration, for callers that stage it:
+ * rollout = sampling, propagation and path costs (fills S and eps, and the
+ * min / normaliser statistics); update = weights and control update (reads
+ * S and eps, updates U, advances the iteration counter).  step == rollout
+ * followed by update. */
+int mppi_jump_rollout(mppi_jump_ctx* ctx, const float* d_x0, void* stream);
+int mppi_jump_update(mppi_jump_ctx* ctx, void* stream);
+
+/* Enqueue the receding-horizon shift (Algorithm 1, after the update):
+ * u0_out[0..m) <- U[0] by a stream-ordered copy (device or host memory; may
+ * be NULL; a host destination is complete once the stream is synchronised),
+ * then U[t] <- U[t+1] and U[T-1] <- u_init. */
+int mppi_jump_shift(mppi_jump_ctx* ctx, float* u0_out, void* stream);
+
+/* Enqueue a copy of an item (MPPI_ITEM_*) into dst (device or host memory).
+ * EINVAL if dst_bytes is smaller than the item; EUNSUPPORTED for a debug
+ * item of a context created without debug_dump.  MPPI_ITEM_W and
+ * MPPI_ITEM_THRESH are computed at call time (W from the current S and
+ * statistics).  A host dst is complete only after the stream is synchronised. */
+int mppi_jump_get(mppi_jump_ctx* ctx, int32_t what, void* dst, size_t dst_bytes, void* stream);
+
+/* Enqueue an overwrite of MPPI_ITEM_U ([T][m] fp32) or MPPI_ITEM_S ([K]
+ * fp64, with the min / normaliser statistics recomputed from it) from src
+ * (device or host).  Setting S between rollout and update lets a caller
+ * supply its own path costs to the update. */
+int mppi_jump_set(mppi_jump_ctx* ctx, int32_t what, const void* src, size_t src_bytes, void* stream);
+
+/* Free the host-side context.  The caller frees the workspace after the
+ * last enqueued work on it has finished. */
+int mppi_jump_destroy(mppi_jump_ctx* ctx);
+
+/* Static text for a status code; never NULL. */
+const char* mppi_jump_strerror(int code);
+
+/* Detail of the calling thread's last failure ("" if none). */
+const char* mppi_jump_last_error(void);
+
+/* ---- closed-loop and measurement helpers (not part of the method) ---- */
+
+/* Simulated plant for closed-loop runs: one explicit Euler step of the
+ * context's dynamics, x <- x + F(x, u + d) dt, on device state d_x ([n]),
+ * applied control d_u ([m]) and disturbance d_dist ([m], added to the
+ * control).  One GPU thread. */
+int mppi_jump_plant_step(mppi_jump_ctx* ctx, float* d_x, const float* d_u,
+                         const float* d_dist, void* stream);
+
+/* Philox4x32-10 blocks of the library's generator for n caller-given
+ * counters: d_out[4i..4i+4) = Philox(d_counters[4i..4i+4), key).  For
+ * checking the generator against an independent implementation. */
+int mppi_jump_philox(const uint32_t* d_counters, uint32_t key0, uint32_t key1,
+                     uint32_t* d_out, int64_t n, void* stream);
+
+/* Timing of the rollout kernel: when enabled, every rollout launch is
+ * bracketed by HIP events on its own stream.  profile_read synchronises on
+ * the recorded events and returns the summed duration (ms) and the launch
+ * count, then clears them.  At most 4096 launches are kept. */
+int mppi_jump_profile(mppi_jump_ctx* ctx, int32_t enable);
+int mppi_jump_profile_read(mppi_jump_ctx* ctx, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPPI_JUMP_H */

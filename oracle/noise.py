@@ -17,7 +17,7 @@ fixed here (also listed in the design notes):
 
 Random words come from Philox4x32-10 (oracle.philox), with
   key     = (seed mod 2^32, seed >> 32)
-  counter = (k, t, iteration mod 2^32, block | controller_id << 8)
+  counter = (t, k, iteration mod 2^32, block | controller_id << 8)
 Per (k, t) the blocks are concatenated into a word stream w[0], w[1], ...
 Normal number i comes from the Box-Muller pair i // 2 (words 2p, 2p+1):
   u = ((w[2p] >> 8) + 1) / 2^24 in (0, 1]     (radius: -2 ln u finite)
@@ -68,8 +68,8 @@ def words(seed, controller_id, iteration, k_index, T, n_blocks):
     t = np.arange(T, dtype=np.uint64)
     for b in range(n_blocks):
         ctr = np.empty((K, T, 4), dtype=np.uint64)
-        ctr[..., 0] = k[:, None]
-        ctr[..., 1] = t[None, :]
+        ctr[..., 0] = t[None, :]
+        ctr[..., 1] = k[:, None]
         ctr[..., 2] = iteration & 0xFFFFFFFF
         ctr[..., 3] = b | (controller_id << 8)
         out[..., 4 * b:4 * b + 4] = philox4x32(ctr, key)

@@ -1,0 +1,170 @@
+"""Python front end of the library: one controller = one context + its
+device workspace.  PyTorch supplies device memory and the stream; every
+computation runs in the library's kernels (through paper_1807_06108_amd.native).
+"""
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import native
+
+_STATS_BYTES = ctypes.sizeof(native.Stats)
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Controller:
+    """MPPI-on-jump-diffusion controller resident on one GPU.
+
+    cfg: configuration dict (keys of mppi_jump_config; see workloads.py).
+    U0: optional initial control sequence [T, m] (default u_init everywhere).
+    """
+
+    def __init__(self, cfg, U0=None, device="cuda", stream=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the controller runs only on the HIP device")
+        self.cfg = dict(cfg)
+        self.device = torch.device(device)
+        self.stream = stream
+        self.n, self.m, self.q = native.dims(cfg["dynamics"])
+        self.K, self.T = int(cfg["K"]), int(cfg["T"])
+        self._c = native.make_config(cfg)
+        self.ws_bytes = native.workspace_bytes(cfg)
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        U0t = None
+        if U0 is not None:
+            U0t = torch.as_tensor(np.asarray(U0, dtype=np.float32).reshape(self.T, self.m),
+                                  device=self.device).contiguous()
+        ctx = ctypes.c_void_p()
+        native.check(native.lib().mppi_jump_init(
+            ctypes.byref(self._c), _ptr(self.ws), self.ws_bytes, _ptr(U0t),
+            _stream_handle(self.stream), ctypes.byref(ctx)))
+        self._keep = U0t
+        self.ctx = ctx
+
+    # ------------------------------------------------------------- lifecycle
+    def close(self):
+        if getattr(self, "ctx", None):
+            native.lib().mppi_jump_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _s(self):
+        return _stream_handle(self.stream)
+
+    def _state(self, x0):
+        x = torch.as_tensor(x0, dtype=torch.float32, device=self.device).contiguous()
+        if x.numel() != self.n:
+            raise ValueError("state needs %d entries" % self.n)
+        return x
+
+    # ------------------------------------------------------------- the method
+    def step(self, x0, iters=1):
+        """Enqueue `iters` iterations from state x0 (tensor or array [n])."""
+        x = self._state(x0)
+        native.check(native.lib().mppi_jump_step(self.ctx, _ptr(x), int(iters), self._s()))
+        return x
+
+    def rollout(self, x0):
+        x = self._state(x0)
+        native.check(native.lib().mppi_jump_rollout(self.ctx, _ptr(x), self._s()))
+        return x
+
+    def update(self):
+        native.check(native.lib().mppi_jump_update(self.ctx, self._s()))
+
+    def shift(self, out=None):
+        """Enqueue the receding-horizon shift; returns the executed u_0 [m]
+        (a device tensor unless `out` is given)."""
+        if out is None:
+            out = torch.empty(self.m, dtype=torch.float32, device=self.device)
+        native.check(native.lib().mppi_jump_shift(self.ctx, _ptr(out), self._s()))
+        return out
+
+    def plant_step(self, x, u, d):
+        """Simulated plant: x <- Euler(x, u + d) on device tensors."""
+        native.check(native.lib().mppi_jump_plant_step(self.ctx, _ptr(x), _ptr(u), _ptr(d), self._s()))
+
+    # ------------------------------------------------------------- items
+    def _get(self, item, nbytes, dtype, shape):
+        out = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        native.check(native.lib().mppi_jump_get(self.ctx, native.ITEM[item], _ptr(out), nbytes, self._s()))
+        return out.view(dtype).reshape(shape)
+
+    @property
+    def U(self):
+        return self._get("U", self.T * self.m * 4, torch.float32, (self.T, self.m))
+
+    @property
+    def S(self):
+        return self._get("S", self.K * 8, torch.float64, (self.K,))
+
+    @property
+    def W(self):
+        return self._get("W", self.K * 8, torch.float64, (self.K,))
+
+    @property
+    def eps(self):
+        """Perturbations, [T, m, K]."""
+        return self._get("EPS", self.T * self.m * self.K * 4, torch.float32, (self.T, self.m, self.K))
+
+    def debug_draws(self):
+        """(z_D [K,T,m], N [K,T], z_J [K,T,q]) of the last rollout."""
+        K, T = self.K, self.T
+        return (self._get("DBG_ZD", K * T * self.m * 4, torch.float32, (K, T, self.m)),
+                self._get("DBG_N", K * T * 4, torch.int32, (K, T)),
+                self._get("DBG_ZJ", K * T * self.q * 4, torch.float32, (K, T, self.q)))
+
+    def stats(self):
+        """Statistics of the last iteration (synchronises)."""
+        raw = self._get("STATS", _STATS_BYTES, torch.uint8, (_STATS_BYTES,)).cpu().numpy()
+        s = native.Stats.from_buffer_copy(raw.tobytes())
+        return dict(rho=s.rho, eta=s.eta, status=s.status, n_finite=s.n_finite,
+                    iteration=s.iteration)
+
+    def set_U(self, U):
+        t = torch.as_tensor(np.asarray(U, dtype=np.float32).reshape(self.T, self.m),
+                            device=self.device).contiguous()
+        native.check(native.lib().mppi_jump_set(self.ctx, native.ITEM["U"], _ptr(t), t.numel() * 4, self._s()))
+        self._keep = t
+
+    def set_S(self, S):
+        t = torch.as_tensor(np.asarray(S, dtype=np.float64).reshape(self.K),
+                            device=self.device).contiguous()
+        native.check(native.lib().mppi_jump_set(self.ctx, native.ITEM["S"], _ptr(t), t.numel() * 8, self._s()))
+        self._keep = t
+
+    # ------------------------------------------------------------- timing
+    def profile(self, enable=True):
+        native.check(native.lib().mppi_jump_profile(self.ctx, int(bool(enable))))
+
+    def profile_read(self):
+        """(summed rollout-kernel ms, launches) since the last read."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        native.check(native.lib().mppi_jump_profile_read(self.ctx, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+
+def philox(counters, key0, key1):
+    """Device Philox4x32-10 blocks for uint32 counters [n, 4] (numpy)."""
+    c = torch.as_tensor(np.ascontiguousarray(counters, dtype=np.uint32).view(np.int32),
+                        device="cuda")
+    out = torch.empty_like(c)
+    n = c.shape[0]
+    native.check(native.lib().mppi_jump_philox(_ptr(c), key0, key1, _ptr(out), n,
+                                               _stream_handle()))
+    return out.cpu().numpy().view(np.uint32)

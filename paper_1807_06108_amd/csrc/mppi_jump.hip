@@ -1,0 +1,615 @@
+// Host side of the C ABI declared in include/mppi_jump.h: configuration
+// validation, workspace layout, kernel dispatch.  See the header for the
+// contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/mppi_jump.h"
+#include "kernels.hpp"
+
+using namespace mppi;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int ok() {
+  g_last_error.clear();
+  return MPPI_OK;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(MPPI_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCH_CHECK(name)                                                                   \
+  do {                                                                                       \
+    hipError_t e_ = hipGetLastError();                                                       \
+    if (e_ != hipSuccess) return fail(MPPI_EDEVICE, "launch of %s: %s", name, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr uint64_t kTwo32 = 1ull << 32;
+
+bool dims_of(int32_t dyn, int& n, int& m, int& q) {
+  switch (dyn) {
+    case MPPI_DYN_LINEAR: n = 2; m = 1; q = 1; return true;
+    case MPPI_DYN_CARTPOLE: n = 4; m = 1; q = 1; return true;
+    case MPPI_DYN_QUADROTOR: n = 12; m = 4; q = 3; return true;
+    default: return false;
+  }
+}
+
+// Inversion thresholds of the count law with mean a = nu * dt, computed in
+// fp64: Poisson CDF by the recurrence p_j = p_{j-1} a / j, or the zero-one
+// law F(0) = 1 - a.  theta_j = floor(F(j) 2^32); the first level reaching
+// 2^32 - 1 closes the table at 2^32.  Returns false if the law needs more
+// than MPPI_JUMP_MAX_LEVELS levels.
+bool count_thresholds(double a, int law, std::vector<uint64_t>& th) {
+  th.clear();
+  if (law == MPPI_COUNT_ZERO_ONE) {
+    if (a > 1.0) return false;
+    double f = std::floor((1.0 - a) * (double)kTwo32);
+    uint64_t t0 = f >= (double)kTwo32 ? kTwo32 : (uint64_t)f;
+    if (t0 < kTwo32) th.push_back(t0);
+    th.push_back(kTwo32);
+    return true;
+  }
+  double p = std::exp(-a), F = p;
+  for (int j = 0; j < MPPI_JUMP_MAX_LEVELS; ++j) {
+    if (j > 0) {
+      p = p * a / j;
+      F = F + p;
+    }
+    const double f = std::floor(F * (double)kTwo32);
+    if (f >= (double)(kTwo32 - 1)) {
+      th.push_back(kTwo32);
+      return true;
+    }
+    th.push_back((uint64_t)f);
+  }
+  return false;
+}
+
+bool finite_pos(float v) { return std::isfinite(v) && v > 0.f; }
+
+int validate(const mppi_jump_config* c, int& n, int& m, int& q, std::vector<uint64_t>& th) {
+  if (!c) return fail(MPPI_EINVAL, "config is NULL");
+  if (c->abi_version != MPPI_JUMP_ABI_VERSION)
+    return fail(MPPI_EINVAL, "abi_version %d != %d", c->abi_version, MPPI_JUMP_ABI_VERSION);
+  if (!dims_of(c->dynamics, n, m, q)) return fail(MPPI_EINVAL, "unknown dynamics %d", c->dynamics);
+  if (c->K < 1 || c->K > MPPI_JUMP_MAX_K) return fail(MPPI_EINVAL, "K=%d out of [1, 2^24]", c->K);
+  if (c->T < 1 || c->T > MPPI_JUMP_MAX_T) return fail(MPPI_EINVAL, "T=%d out of [1, 4096]", c->T);
+  if (!finite_pos(c->dt)) return fail(MPPI_EINVAL, "dt must be finite and > 0");
+  if (!finite_pos(c->lambda)) return fail(MPPI_EINVAL, "lambda must be finite and > 0");
+  if (!finite_pos(c->c)) return fail(MPPI_EINVAL, "c must be finite and > 0");
+  if (!std::isfinite(c->alpha)) return fail(MPPI_EINVAL, "alpha must be finite");
+  if (!(std::isfinite(c->nu) && c->nu >= 0.f)) return fail(MPPI_EINVAL, "nu must be finite and >= 0");
+  if (c->count_law != MPPI_COUNT_POISSON && c->count_law != MPPI_COUNT_ZERO_ONE)
+    return fail(MPPI_EINVAL, "unknown count_law %d", c->count_law);
+  if (c->cost_form != MPPI_COST_IT && c->cost_form != MPPI_COST_SO)
+    return fail(MPPI_EINVAL, "unknown cost_form %d", c->cost_form);
+  if (c->debug_dump != 0 && c->debug_dump != 1) return fail(MPPI_EINVAL, "debug_dump must be 0 or 1");
+  if (c->reserved != 0) return fail(MPPI_EINVAL, "reserved must be 0");
+  for (int j = 0; j < m; ++j)
+    if (!(std::isfinite(c->sigma[j]) && c->sigma[j] >= 0.f))
+      return fail(MPPI_EINVAL, "sigma[%d] must be finite and >= 0", j);
+  for (int i = 0; i < q; ++i)
+    if (!(std::isfinite(c->sigma_J[i]) && c->sigma_J[i] >= 0.f))
+      return fail(MPPI_EINVAL, "sigma_J[%d] must be finite and >= 0", i);
+  for (int j = 0; j < m; ++j)
+    if (!std::isfinite(c->u_init[j]) || !std::isfinite(c->R[j]))
+      return fail(MPPI_EINVAL, "u_init / R must be finite");
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(c->Q[i]) || !std::isfinite(c->Qf[i]) || !std::isfinite(c->x_goal[i]))
+      return fail(MPPI_EINVAL, "Q / Qf / x_goal must be finite");
+  if (!std::isfinite(c->crash_penalty)) return fail(MPPI_EINVAL, "crash_penalty must be finite");
+  if (c->controller_id >= (1ull << 24)) return fail(MPPI_EINVAL, "controller_id must be < 2^24");
+  if (c->start_iteration >= kTwo32) return fail(MPPI_EINVAL, "start_iteration must be < 2^32");
+  const float* P = c->params;
+  if (c->dynamics == MPPI_DYN_CARTPOLE) {
+    if (!finite_pos(P[0]) || !finite_pos(P[1]) || !finite_pos(P[2]) || !std::isfinite(P[3]))
+      return fail(MPPI_EINVAL, "cartpole params need m_cart, m_pole, half_length > 0, finite g");
+  } else if (c->dynamics == MPPI_DYN_QUADROTOR) {
+    for (int i = 0; i < 5; ++i)
+      if (!finite_pos(P[i])) return fail(MPPI_EINVAL, "quadrotor mass, J, arm must be > 0");
+    if (!std::isfinite(P[5]) || !std::isfinite(P[6]) || !std::isfinite(P[8]))
+      return fail(MPPI_EINVAL, "quadrotor k_yaw, g, z_min must be finite");
+    if (!(P[7] > 0.f && P[7] < 1.5f)) return fail(MPPI_EINVAL, "quadrotor tilt_max must be in (0, 1.5)");
+  }
+  const double a = (double)c->nu * (double)c->dt;
+  if (!count_thresholds(a, c->count_law, th))
+    return fail(MPPI_EINVAL, "jump mean nu*dt=%g does not fit the count law table", a);
+  return MPPI_OK;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+  int R, Ks, nwg, nch, chunk;
+  size_t U, eps, S, E, part, scale, upart, stats, counters, W, zD, N, zJ, total;
+};
+
+Layout make_layout(const mppi_jump_config* c, int m, int q) {
+  Layout L{};
+  const size_t K = (size_t)c->K, T = (size_t)c->T;
+  L.R = (int)(T * m);
+  L.Ks = (int)align_up(K, 64);
+  L.nwg = (int)((K + kBlock - 1) / kBlock);
+  int nch = (int)((K + 1023) / 1024);
+  if (nch > 64) nch = 64;
+  L.chunk = (int)align_up((K + nch - 1) / nch, kBlock);
+  L.nch = (int)((K + L.chunk - 1) / L.chunk);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes, 256);
+    return at;
+  };
+  L.U = take((size_t)L.R * 4);
+  L.eps = take((size_t)L.R * L.Ks * 4);
+  L.S = take(K * 8);
+  L.E = take(K * 8);
+  L.part = take((size_t)L.nwg * sizeof(WgPartial));
+  L.scale = take((size_t)L.nwg * 8);
+  L.upart = take((size_t)L.R * L.nch * 8);
+  L.stats = take(sizeof(mppi_jump_stats));
+  L.counters = take(2 * sizeof(uint32_t));
+  L.W = take(K * 8);
+  if (c->debug_dump) {
+    L.zD = take(K * T * m * 4);
+    L.N = take(K * T * 4);
+    L.zJ = take(K * T * q * 4);
+  }
+  L.total = off;
+  return L;
+}
+
+DevParams make_params(const mppi_jump_config* c, int n, int m, int q, const Layout& L,
+                      const std::vector<uint64_t>& th) {
+  DevParams p;
+  std::memset(&p, 0, sizeof p);
+  p.K = c->K;
+  p.T = c->T;
+  p.Ks = L.Ks;
+  p.key0 = (uint32_t)(c->seed & 0xFFFFFFFFull);
+  p.key1 = (uint32_t)(c->seed >> 32);
+  p.ctr3 = (uint32_t)(c->controller_id << 8);
+  p.cost_form = c->cost_form;
+  p.dt = c->dt;
+  p.lam = c->lambda;
+  p.lam_d = (double)c->lambda;
+  p.alpha = c->alpha;
+  p.pen = c->crash_penalty;
+  const double lam = c->lambda, cc = c->c;
+  for (int j = 0; j < m; ++j) {
+    p.sigma[j] = c->sigma[j];
+    const double s2 = (double)c->sigma[j] * (double)c->sigma[j];
+    p.isc[j] = s2 > 0 ? (float)(lam * cc / s2) : 0.f;
+    p.isv[j] = s2 > 0 ? (float)(0.5 * lam * (cc - 1.0) / s2) : 0.f;
+    p.halfR[j] = 0.5f * c->R[j];
+  }
+  for (int i = 0; i < q; ++i) p.sigJ[i] = c->sigma_J[i];
+  for (int i = 0; i < n; ++i) {
+    p.Q[i] = c->Q[i];
+    p.Qf[i] = c->Qf[i];
+    p.goal[i] = c->x_goal[i];
+  }
+  const float* P = c->params;
+  if (c->dynamics == MPPI_DYN_CARTPOLE) {
+    const double mc = P[0], mp = P[1], l = P[2], g = P[3];
+    p.mc.c[0] = (float)g;
+    p.mc.c[1] = (float)(1.0 / (mc + mp));
+    p.mc.c[2] = (float)(mp * l);
+    p.mc.c[3] = (float)(mp * l / (mc + mp));
+    p.mc.c[4] = (float)(4.0 / 3.0 * l);
+  } else if (c->dynamics == MPPI_DYN_QUADROTOR) {
+    const double mass = P[0], Jx = P[1], Jy = P[2], Jz = P[3];
+    p.mc.c[0] = (float)(1.0 / mass);
+    p.mc.c[1] = (float)(1.0 / Jx);
+    p.mc.c[2] = (float)(1.0 / Jy);
+    p.mc.c[3] = (float)(1.0 / Jz);
+    p.mc.c[4] = (float)(Jz - Jy);
+    p.mc.c[5] = (float)(Jx - Jz);
+    p.mc.c[6] = (float)(Jy - Jx);
+    p.mc.c[7] = P[4];
+    p.mc.c[8] = P[5];
+    p.mc.c[9] = P[6];
+    p.mc.c[10] = P[7];
+    p.mc.c[11] = P[8];
+  }
+  p.n_th = 0;
+  for (size_t j = 0; j < th.size() && j < MPPI_JUMP_MAX_LEVELS; ++j)
+    if (th[j] < kTwo32) p.th[p.n_th++] = (uint32_t)th[j];
+  return p;
+}
+
+}  // namespace
+
+struct mppi_jump_ctx {
+  mppi_jump_config cfg;
+  int n, m, q;
+  Layout L;
+  DevParams p;
+  Buffers b;
+  double* W;
+  uint64_t th64[MPPI_JUMP_MAX_LEVELS];
+  uint64_t host_iteration;  // iterations enqueued so far (range check only)
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t events_used = 0;
+};
+
+namespace {
+
+template <int DYN>
+int launch_rollout_dyn(mppi_jump_ctx* ctx, const float* x0, hipStream_t s) {
+  const dim3 grid(ctx->L.nwg), block(kBlock);
+  const bool jumps = ctx->p.n_th > 0, dbg = ctx->cfg.debug_dump != 0;
+  if (jumps) {
+    if (dbg)
+      rollout_kernel<DYN, true, true><<<grid, block, 0, s>>>(ctx->p, ctx->b, x0, ctx->b.U);
+    else
+      rollout_kernel<DYN, true, false><<<grid, block, 0, s>>>(ctx->p, ctx->b, x0, ctx->b.U);
+  } else {
+    if (dbg)
+      rollout_kernel<DYN, false, true><<<grid, block, 0, s>>>(ctx->p, ctx->b, x0, ctx->b.U);
+    else
+      rollout_kernel<DYN, false, false><<<grid, block, 0, s>>>(ctx->p, ctx->b, x0, ctx->b.U);
+  }
+  LAUNCH_CHECK("rollout_kernel");
+  return MPPI_OK;
+}
+
+int launch_rollout(mppi_jump_ctx* ctx, const float* x0, hipStream_t s) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->profiling) {
+    if (ctx->events_used >= 4096) return fail(MPPI_EINVAL, "profiling buffer full (4096 launches)");
+    if (ctx->events_used == ctx->events.size()) {
+      HIP_TRY(hipEventCreate(&e0));
+      HIP_TRY(hipEventCreate(&e1));
+      ctx->events.emplace_back(e0, e1);
+    }
+    e0 = ctx->events[ctx->events_used].first;
+    e1 = ctx->events[ctx->events_used].second;
+    HIP_TRY(hipEventRecord(e0, s));
+  }
+  int rc;
+  switch (ctx->cfg.dynamics) {
+    case MPPI_DYN_LINEAR: rc = launch_rollout_dyn<MPPI_DYN_LINEAR>(ctx, x0, s); break;
+    case MPPI_DYN_CARTPOLE: rc = launch_rollout_dyn<MPPI_DYN_CARTPOLE>(ctx, x0, s); break;
+    default: rc = launch_rollout_dyn<MPPI_DYN_QUADROTOR>(ctx, x0, s); break;
+  }
+  if (rc != MPPI_OK) return rc;
+  if (ctx->profiling) {
+    HIP_TRY(hipEventRecord(e1, s));
+    ctx->events_used++;
+  }
+  return MPPI_OK;
+}
+
+int launch_update(mppi_jump_ctx* ctx, hipStream_t s) {
+  const dim3 grid((ctx->L.R + kRowsPerWg - 1) / kRowsPerWg, ctx->L.nch), block(kBlock);
+  update_kernel<<<grid, block, 0, s>>>(ctx->p, ctx->b, ctx->L.R, ctx->L.nch, ctx->L.chunk);
+  LAUNCH_CHECK("update_kernel");
+  return MPPI_OK;
+}
+
+float4 u_init4(const mppi_jump_config& c) {
+  return make_float4(c.u_init[0], c.u_init[1], c.u_init[2], c.u_init[3]);
+}
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(MPPI_EDEVICE, "host allocation failed");
+  } catch (...) {
+    return fail(MPPI_EDEVICE, "unexpected exception");
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mppi_jump_abi_version(void) { return MPPI_JUMP_ABI_VERSION; }
+
+int mppi_jump_dims(int32_t dynamics, int32_t* n, int32_t* m, int32_t* q) {
+  int nn, mm, qq;
+  if (!n || !m || !q) return fail(MPPI_EINVAL, "NULL output");
+  if (!dims_of(dynamics, nn, mm, qq)) return fail(MPPI_EINVAL, "unknown dynamics %d", dynamics);
+  *n = nn;
+  *m = mm;
+  *q = qq;
+  return ok();
+}
+
+int mppi_jump_workspace_bytes(const mppi_jump_config* cfg, size_t* bytes) {
+  return guarded([&]() -> int {
+    if (!bytes) return fail(MPPI_EINVAL, "bytes is NULL");
+    int n, m, q;
+    std::vector<uint64_t> th;
+    const int rc = validate(cfg, n, m, q, th);
+    if (rc != MPPI_OK) return rc;
+    *bytes = make_layout(cfg, m, q).total;
+    return ok();
+  });
+}
+
+int mppi_jump_count_thresholds(const mppi_jump_config* cfg, uint64_t* out) {
+  return guarded([&]() -> int {
+    if (!out) return fail(MPPI_EINVAL, "out is NULL");
+    int n, m, q;
+    std::vector<uint64_t> th;
+    const int rc = validate(cfg, n, m, q, th);
+    if (rc != MPPI_OK) return rc;
+    for (int j = 0; j < MPPI_JUMP_MAX_LEVELS; ++j) out[j] = j < (int)th.size() ? th[j] : kTwo32;
+    return ok();
+  });
+}
+
+int mppi_jump_init(const mppi_jump_config* cfg, void* d_workspace, size_t ws_bytes,
+                   const float* d_U0, void* stream, mppi_jump_ctx** out) {
+  return guarded([&]() -> int {
+    if (!out) return fail(MPPI_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n, m, q;
+    std::vector<uint64_t> th;
+    int rc = validate(cfg, n, m, q, th);
+    if (rc != MPPI_OK) return rc;
+    const Layout L = make_layout(cfg, m, q);
+    if (!d_workspace || ((uintptr_t)d_workspace & 255u))
+      return fail(MPPI_EWORKSPACE, "workspace must be a 256-byte aligned device pointer");
+    if (ws_bytes < L.total)
+      return fail(MPPI_EWORKSPACE, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
+    auto* ctx = new mppi_jump_ctx();
+    ctx->cfg = *cfg;
+    ctx->n = n;
+    ctx->m = m;
+    ctx->q = q;
+    ctx->L = L;
+    ctx->p = make_params(cfg, n, m, q, L, th);
+    for (int j = 0; j < MPPI_JUMP_MAX_LEVELS; ++j) ctx->th64[j] = j < (int)th.size() ? th[j] : kTwo32;
+    char* base = static_cast<char*>(d_workspace);
+    Buffers& b = ctx->b;
+    b.U = reinterpret_cast<float*>(base + L.U);
+    b.eps = reinterpret_cast<float*>(base + L.eps);
+    b.S = reinterpret_cast<double*>(base + L.S);
+    b.E = reinterpret_cast<double*>(base + L.E);
+    b.part = reinterpret_cast<WgPartial*>(base + L.part);
+    b.scale = reinterpret_cast<double*>(base + L.scale);
+    b.upart = reinterpret_cast<double*>(base + L.upart);
+    b.stats = reinterpret_cast<mppi_jump_stats*>(base + L.stats);
+    b.counters = reinterpret_cast<uint32_t*>(base + L.counters);
+    ctx->W = reinterpret_cast<double*>(base + L.W);
+    b.dbg_zD = cfg->debug_dump ? reinterpret_cast<float*>(base + L.zD) : nullptr;
+    b.dbg_N = cfg->debug_dump ? reinterpret_cast<int32_t*>(base + L.N) : nullptr;
+    b.dbg_zJ = cfg->debug_dump ? reinterpret_cast<float*>(base + L.zJ) : nullptr;
+    ctx->host_iteration = cfg->start_iteration;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int threads = 256, blocks = (L.R + threads - 1) / threads;
+    init_kernel<<<blocks, threads, 0, s>>>(b, d_U0, L.R, m, u_init4(*cfg), cfg->start_iteration);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      delete ctx;
+      return fail(MPPI_EDEVICE, "launch of init_kernel: %s", hipGetErrorString(e));
+    }
+    *out = ctx;
+    return ok();
+  });
+}
+
+int mppi_jump_rollout(mppi_jump_ctx* ctx, const float* d_x0, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx || !d_x0) return fail(MPPI_EINVAL, "NULL context or state");
+    const int rc = launch_rollout(ctx, d_x0, static_cast<hipStream_t>(stream));
+    return rc == MPPI_OK ? ok() : rc;
+  });
+}
+
+int mppi_jump_update(mppi_jump_ctx* ctx, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(MPPI_EINVAL, "NULL context");
+    if (ctx->host_iteration + 1 > kTwo32) return fail(MPPI_EINVAL, "iteration counter exhausted");
+    const int rc = launch_update(ctx, static_cast<hipStream_t>(stream));
+    if (rc != MPPI_OK) return rc;
+    ctx->host_iteration += 1;
+    return ok();
+  });
+}
+
+int mppi_jump_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx || !d_x0) return fail(MPPI_EINVAL, "NULL context or state");
+    if (iters < 1) return fail(MPPI_EINVAL, "iters=%d < 1", iters);
+    if (ctx->host_iteration + (uint64_t)iters > kTwo32)
+      return fail(MPPI_EINVAL, "iteration counter would pass 2^32");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < iters; ++i) {
+      int rc = launch_rollout(ctx, d_x0, s);
+      if (rc != MPPI_OK) return rc;
+      rc = launch_update(ctx, s);
+      if (rc != MPPI_OK) return rc;
+      ctx->host_iteration += 1;
+    }
+    return ok();
+  });
+}
+
+int mppi_jump_shift(mppi_jump_ctx* ctx, float* u0_out, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx) return fail(MPPI_EINVAL, "NULL context");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    // u_0 leaves by a stream-ordered copy (device or host destination)
+    if (u0_out) HIP_TRY(hipMemcpyAsync(u0_out, ctx->b.U, (size_t)ctx->m * 4, hipMemcpyDefault, s));
+    shift_kernel<<<1, 1024, 0, s>>>(ctx->b.U, ctx->L.R, ctx->m, u_init4(ctx->cfg));
+    LAUNCH_CHECK("shift_kernel");
+    return ok();
+  });
+}
+
+int mppi_jump_get(mppi_jump_ctx* ctx, int32_t what, void* dst, size_t dst_bytes, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx || !dst) return fail(MPPI_EINVAL, "NULL context or destination");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t K = (size_t)ctx->cfg.K, T = (size_t)ctx->cfg.T;
+    auto need = [&](size_t bytes) -> int {
+      if (dst_bytes < bytes) return fail(MPPI_EINVAL, "destination of %zu bytes < %zu", dst_bytes, bytes);
+      return MPPI_OK;
+    };
+    const void* src = nullptr;
+    size_t bytes = 0;
+    switch (what) {
+      case MPPI_ITEM_U: src = ctx->b.U; bytes = (size_t)ctx->L.R * 4; break;
+      case MPPI_ITEM_S: src = ctx->b.S; bytes = K * 8; break;
+      case MPPI_ITEM_STATS: src = ctx->b.stats; bytes = sizeof(mppi_jump_stats); break;
+      case MPPI_ITEM_W: {
+        if (need(K * 8) != MPPI_OK) return MPPI_EINVAL;
+        weights_kernel<<<(unsigned)((K + 255) / 256), 256, 0, s>>>(ctx->p, ctx->b, ctx->W);
+        LAUNCH_CHECK("weights_kernel");
+        src = ctx->W;
+        bytes = K * 8;
+        break;
+      }
+      case MPPI_ITEM_EPS: {
+        if (need((size_t)ctx->L.R * K * 4) != MPPI_OK) return MPPI_EINVAL;
+        HIP_TRY(hipMemcpy2DAsync(dst, K * 4, ctx->b.eps, (size_t)ctx->L.Ks * 4, K * 4,
+                                 (size_t)ctx->L.R, hipMemcpyDefault, s));
+        return ok();
+      }
+      case MPPI_ITEM_DBG_ZD:
+      case MPPI_ITEM_DBG_N:
+      case MPPI_ITEM_DBG_ZJ:
+        if (!ctx->cfg.debug_dump) return fail(MPPI_EUNSUPPORTED, "context was created without debug_dump");
+        if (what == MPPI_ITEM_DBG_ZD) { src = ctx->b.dbg_zD; bytes = K * T * ctx->m * 4; }
+        if (what == MPPI_ITEM_DBG_N) { src = ctx->b.dbg_N; bytes = K * T * 4; }
+        if (what == MPPI_ITEM_DBG_ZJ) { src = ctx->b.dbg_zJ; bytes = K * T * ctx->q * 4; }
+        break;
+      case MPPI_ITEM_THRESH: src = ctx->th64; bytes = sizeof(ctx->th64); break;
+      default: return fail(MPPI_EINVAL, "unknown item %d", what);
+    }
+    if (need(bytes) != MPPI_OK) return MPPI_EINVAL;
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, s));
+    return ok();
+  });
+}
+
+int mppi_jump_set(mppi_jump_ctx* ctx, int32_t what, const void* src, size_t src_bytes, void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx || !src) return fail(MPPI_EINVAL, "NULL context or source");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (what == MPPI_ITEM_U) {
+      const size_t bytes = (size_t)ctx->L.R * 4;
+      if (src_bytes != bytes) return fail(MPPI_EINVAL, "U needs %zu bytes, got %zu", bytes, src_bytes);
+      HIP_TRY(hipMemcpyAsync(ctx->b.U, src, bytes, hipMemcpyDefault, s));
+      return ok();
+    }
+    if (what == MPPI_ITEM_S) {
+      const size_t bytes = (size_t)ctx->cfg.K * 8;
+      if (src_bytes != bytes) return fail(MPPI_EINVAL, "S needs %zu bytes, got %zu", bytes, src_bytes);
+      HIP_TRY(hipMemcpyAsync(ctx->b.S, src, bytes, hipMemcpyDefault, s));
+      restats_kernel<<<ctx->L.nwg, kBlock, 0, s>>>(ctx->p, ctx->b);
+      LAUNCH_CHECK("restats_kernel");
+      return ok();
+    }
+    return fail(MPPI_EINVAL, "item %d cannot be set", what);
+  });
+}
+
+int mppi_jump_destroy(mppi_jump_ctx* ctx) {
+  if (!ctx) return ok();
+  for (auto& e : ctx->events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  delete ctx;
+  return ok();
+}
+
+const char* mppi_jump_strerror(int code) {
+  switch (code) {
+    case MPPI_OK: return "ok";
+    case MPPI_EINVAL: return "invalid argument";
+    case MPPI_EWORKSPACE: return "workspace too small or misaligned";
+    case MPPI_EDEVICE: return "HIP runtime error";
+    case MPPI_ENONFINITE: return "all path costs non-finite";
+    case MPPI_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status code";
+  }
+}
+
+const char* mppi_jump_last_error(void) { return g_last_error.c_str(); }
+
+int mppi_jump_plant_step(mppi_jump_ctx* ctx, float* d_x, const float* d_u, const float* d_dist,
+                         void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx || !d_x || !d_u || !d_dist) return fail(MPPI_EINVAL, "NULL argument");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    switch (ctx->cfg.dynamics) {
+      case MPPI_DYN_LINEAR: plant_kernel<MPPI_DYN_LINEAR><<<1, 64, 0, s>>>(ctx->p, d_x, d_u, d_dist); break;
+      case MPPI_DYN_CARTPOLE: plant_kernel<MPPI_DYN_CARTPOLE><<<1, 64, 0, s>>>(ctx->p, d_x, d_u, d_dist); break;
+      default: plant_kernel<MPPI_DYN_QUADROTOR><<<1, 64, 0, s>>>(ctx->p, d_x, d_u, d_dist); break;
+    }
+    LAUNCH_CHECK("plant_kernel");
+    return ok();
+  });
+}
+
+int mppi_jump_philox(const uint32_t* d_counters, uint32_t key0, uint32_t key1, uint32_t* d_out,
+                     int64_t n, void* stream) {
+  return guarded([&]() -> int {
+    if (n < 0 || (n > 0 && (!d_counters || !d_out))) return fail(MPPI_EINVAL, "bad arguments");
+    if (n == 0) return ok();
+    if (n > (1ll << 30)) return fail(MPPI_EINVAL, "n too large");
+    philox_kernel<<<(unsigned)((n + 255) / 256), 256, 0, static_cast<hipStream_t>(stream)>>>(
+        d_counters, key0, key1, d_out, n);
+    LAUNCH_CHECK("philox_kernel");
+    return ok();
+  });
+}
+
+int mppi_jump_profile(mppi_jump_ctx* ctx, int32_t enable) {
+  if (!ctx) return fail(MPPI_EINVAL, "NULL context");
+  ctx->profiling = enable != 0;
+  return ok();
+}
+
+int mppi_jump_profile_read(mppi_jump_ctx* ctx, double* total_ms, int64_t* launches) {
+  return guarded([&]() -> int {
+    if (!ctx || !total_ms || !launches) return fail(MPPI_EINVAL, "NULL argument");
+    double tot = 0.0;
+    for (size_t i = 0; i < ctx->events_used; ++i) {
+      HIP_TRY(hipEventSynchronize(ctx->events[i].second));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, ctx->events[i].first, ctx->events[i].second));
+      tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int64_t)ctx->events_used;
+    ctx->events_used = 0;
+    return ok();
+  });
+}
+
+}  // extern "C"

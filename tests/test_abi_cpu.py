@@ -1,0 +1,127 @@
+"""C-ABI checks that need no GPU: the library loads and exports every entry
+point the header declares, the ctypes structures match the C layout, and the
+pure host functions (dimensions, workspace sizing, validation, count tables,
+status strings) behave as documented."""
+
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import noise
+from paper_1807_06108_amd import native, workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(native.HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char\*)\s+(mppi_jump_\w+)\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared_functions()
+    assert len(names) >= 18
+    lib = native.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    # every binding prototype is declared in the header
+    assert set(native._PROTOS) <= set(names)
+    out = subprocess.run(["nm", "-D", "--defined-only", native.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (mppi_jump_\w+)$", out, re.M))
+    assert set(names) <= exported
+
+
+def test_struct_layout_matches_c(tmp_path):
+    fields = [f for f, _ in native.Config._fields_]
+    cfields = [("lambda" if f == "lambda_" else f) for f in fields]
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "mppi_jump.h"', "int main(void){",
+           'printf("%zu %zu\\n", sizeof(mppi_jump_config), sizeof(mppi_jump_stats));']
+    src += ['printf("%%zu\\n", offsetof(mppi_jump_config, %s));' % f for f in cfields]
+    src += ['printf("%%zu\\n", offsetof(mppi_jump_stats, %s));' % f for f, _ in native.Stats._fields_]
+    src += ["return 0;}"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(c)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                           check=True).stdout.split()]
+    import ctypes
+    assert vals[0] == ctypes.sizeof(native.Config) and vals[1] == ctypes.sizeof(native.Stats)
+    offs = [getattr(native.Config, f).offset for f in fields]
+    offs += [getattr(native.Stats, f).offset for f, _ in native.Stats._fields_]
+    assert vals[2:] == offs
+
+
+def test_version_dims_strerror():
+    assert native.lib().mppi_jump_abi_version() == native.C["MPPI_JUMP_ABI_VERSION"]
+    assert native.dims(0) == (2, 1, 1)
+    assert native.dims(1) == (4, 1, 1)
+    assert native.dims(2) == (12, 4, 3)
+    with pytest.raises(native.MppiError) as e:
+        native.dims(7)
+    assert e.value.code == native.C["MPPI_EINVAL"] and "unknown dynamics" in str(e.value)
+    for code in (0, -1, -2, -3, -4, -5, 99):
+        assert native.strerror(code)
+
+
+def test_workspace_bytes_scales_with_the_problem():
+    small = native.workspace_bytes(workloads.cartpole())
+    big = native.workspace_bytes(workloads.cartpole_mpc())
+    quad = native.workspace_bytes(workloads.quadrotor())
+    assert small > 256 * 50 * 4
+    assert big >= 4096 * 100 * 4 + 4096 * 16
+    assert quad >= 8192 * 100 * 4 * 4
+    dbg = native.workspace_bytes(dict(workloads.cartpole(), debug_dump=1))
+    assert dbg >= small + 256 * 50 * 12
+
+
+BAD = [
+    ("dynamics", 3), ("K", 0), ("K", 2**24 + 1), ("T", 0), ("T", 4097), ("dt", 0.0),
+    ("dt", float("nan")), ("lambda", 0.0), ("lambda", -1.0), ("c", 0.0), ("nu", -0.1),
+    ("nu", float("inf")), ("alpha", float("nan")), ("count_law", 2), ("cost_form", 5),
+    ("debug_dump", 3), ("reserved", 1), ("sigma", [-1.0, 0, 0, 0]),
+    ("sigma_J", [float("nan"), 0, 0, 0]), ("controller_id", 2**24),
+    ("start_iteration", 2**32), ("params", [0.0] * 12),
+]
+
+
+@pytest.mark.parametrize("field,value", BAD)
+def test_invalid_config_is_rejected(field, value):
+    cfg = workloads.cartpole()
+    cfg[field] = value
+    with pytest.raises(native.MppiError) as e:
+        native.workspace_bytes(cfg)
+    assert e.value.code == native.C["MPPI_EINVAL"]
+
+
+def test_abi_version_mismatch_and_jump_table_overflow():
+    c = native.make_config(workloads.cartpole())
+    c.abi_version = 99
+    import ctypes
+    b = ctypes.c_size_t()
+    assert native.lib().mppi_jump_workspace_bytes(ctypes.byref(c), ctypes.byref(b)) == native.C["MPPI_EINVAL"]
+    with pytest.raises(native.MppiError):
+        native.workspace_bytes(workloads.cartpole(nu=2000.0))        # nu dt = 40
+    with pytest.raises(native.MppiError):
+        native.workspace_bytes(workloads.cartpole(nu=60.0, count_law=1))  # zero-one needs nu dt <= 1
+    q = workloads.quadrotor()
+    q["params"] = list(q["params"])
+    q["params"][7] = 1.6
+    with pytest.raises(native.MppiError):
+        native.workspace_bytes(q)
+
+
+@pytest.mark.parametrize("nu,law,dt", [(0.0, 0, 0.02), (2.0, 0, 0.02), (5.0, 0, 0.02),
+                                       (3.0, 0, 0.01), (10.0, 0, 0.02), (10.0, 1, 0.02),
+                                       (50.0, 0, 0.05), (0.5, 1, 0.1), (49.0, 1, 0.02)])
+def test_count_tables_equal_the_oracle(nu, law, dt):
+    cfg = workloads.cartpole(nu=nu, count_law=law, dt=dt)
+    lib_th = native.count_thresholds(cfg)
+    a = float(np.float32(nu)) * float(np.float32(dt))
+    ref = noise.count_thresholds(a, law)
+    assert lib_th[:len(ref)] == ref
+    assert all(v == 2**32 for v in lib_th[len(ref):])

@@ -1,0 +1,314 @@
+"""Parity of the HIP path with the FP64 oracle on the same seeded inputs.
+
+Tolerances (stated by the task contract of the method): path costs within
+1e-4 relative (to max(|S|, 1)); the control update within 1e-5 absolute when
+the update is fed the oracle's costs (staged), because fp32 rollout error in
+S is amplified by 1/lambda in the weights; end to end within the first-order
+bound of that amplification.  Integer work (Philox words, jump counts) is
+compared bitwise."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import (S_RTOL, U_ATOL, check_S, near_crash, run_rollout, s_rel_err,
+                      staged_update)
+from oracle import mppi as omppi
+from oracle import noise, philox
+from paper_1807_06108_amd import native, workloads
+from paper_1807_06108_amd.controller import Controller, philox as dev_philox
+
+pytestmark = pytest.mark.gpu
+
+
+def test_device_philox_is_bitwise_the_oracle():
+    rng = np.random.default_rng(0)
+    ctr = rng.integers(0, 2**32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    for key in [(0, 0), (0xDEADBEEF, 0x12345678), (0xFFFFFFFF, 0xFFFFFFFF)]:
+        got = dev_philox(ctr, *key)
+        ref = philox.philox4x32(ctr.astype(np.uint64), key)
+        assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("preset,over", [
+    ("cartpole_single", {}), ("cartpole_single", dict(count_law=1, nu=10.0)),
+    ("quadrotor_hover", dict(K=512, T=40)), ("double_integrator", {}),
+    ("cartpole_single", dict(nu=0.0)),
+])
+def test_noise_draws_match_oracle(preset, over):
+    cfg = workloads.PRESETS[preset](debug_dump=1, **over)
+    ctl, ref, _, _ = run_rollout(cfg)
+    zD, N, zJ = [t.cpu().numpy() for t in ctl.debug_draws()]
+    assert np.array_equal(N, ref["N"])
+    assert np.abs(zD - ref["z_D"]).max() < 1e-5
+    if cfg["nu"] > 0:
+        assert np.abs(zJ - ref["z_J"]).max() < 1e-5
+    eps = ctl.eps.cpu().numpy().transpose(2, 0, 1)
+    scale = max(1.0, float(np.max(cfg["sigma_J"])))
+    assert np.abs(eps - ref["eps"]).max() < 1e-5 * scale * 6
+
+
+@pytest.mark.parametrize("K,T", [(256, 50), (1000, 50), (257, 7), (1, 5), (64, 1), (300, 100)])
+@pytest.mark.parametrize("kind", ["nominal", "random"])
+def test_cartpole_costs_and_staged_update(K, T, kind):
+    cfg = workloads.cartpole(K=K, T=T)
+    U0 = workloads.U0_for(cfg, kind)
+    ctl, ref, _, _ = run_rollout(cfg, U0=U0)
+    check_S(ctl, ref)
+    staged_update(ctl, ref)
+
+
+def test_quadrotor_costs_and_staged_update():
+    cfg = workloads.quadrotor(K=1024, T=100)
+    U0 = workloads.U0_for(cfg, "random")
+    ctl, ref, _, _ = run_rollout(cfg, U0=U0)
+    excl = near_crash(ref)
+    S, err = check_S(ctl, ref, exclude=excl)
+    print("quadrotor: %d near-threshold samples excluded, max rel err %.2e" % (excl.sum(), err))
+    assert excl.sum() < 0.03 * cfg["K"]
+    staged_update(ctl, ref)
+
+
+def test_quadrotor_crashes_are_penalised():
+    cfg = workloads.quadrotor(K=512, T=100, sigma=[1.0] * 4)
+    ctl, ref, _, _ = run_rollout(cfg)
+    S = ctl.S.cpu().numpy()
+    crashed = ref["S"] > 1e4
+    assert crashed.any() and (~crashed).any()
+    keep = ~near_crash(ref)
+    assert np.array_equal((S > 1e4)[keep], crashed[keep])
+
+
+@pytest.mark.parametrize("over", [dict(nu=0.0), dict(count_law=1, nu=20.0), dict(cost_form=1),
+                                  dict(c=2.0), dict(alpha=0.3), dict(controller_id=77, seed=5),
+                                  dict(start_iteration=123456)])
+def test_cartpole_variants(over):
+    cfg = workloads.cartpole(**over)
+    U0 = workloads.U0_for(cfg, "random")
+    ctl, ref, _, _ = run_rollout(cfg, U0=U0)
+    check_S(ctl, ref)
+    staged_update(ctl, ref)
+
+
+def test_double_integrator():
+    cfg = workloads.double_integrator(K=777, T=33)
+    U0 = workloads.U0_for(cfg, "random")
+    ctl, ref, _, _ = run_rollout(cfg, U0=U0)
+    check_S(ctl, ref)
+    staged_update(ctl, ref)
+
+
+def test_end_to_end_within_first_order_bound():
+    for kind in ("nominal", "random"):
+        cfg = workloads.cartpole()
+        U0 = workloads.U0_for(cfg, kind)
+        ctl = Controller(cfg, U0)
+        x0 = workloads.x0_for(cfg)
+        ctl.step(x0, 1)
+        ref = omppi.iteration(cfg, x0, U0.astype(np.float64), 0)
+        S = ctl.S.cpu().numpy()
+        dS = np.abs(S - ref["S"]).max()
+        eps = ref["eps"]
+        spread = (ref["w"][:, None, None] * np.abs(eps - np.einsum("k,ktj->tj", ref["w"], eps))).sum(0)
+        bound = U_ATOL + 2.0 * dS / cfg["lambda"] * spread
+        err = np.abs(ctl.U.cpu().numpy() - ref["U"])
+        print("e2e %s: max err %.2e, max bound %.2e" % (kind, err.max(), bound.max()))
+        assert (err <= bound).all()
+
+
+def test_zero_noise_leaves_U_bitwise_unchanged():
+    cfg = workloads.cartpole(sigma=[0.0] * 4, nu=0.0)
+    U0 = workloads.U0_for(cfg, "random")
+    ctl = Controller(cfg, U0)
+    ctl.step(workloads.x0_for(cfg), 3)
+    assert np.array_equal(ctl.U.cpu().numpy(), U0)
+    W = ctl.W.cpu().numpy()
+    assert np.array_equal(W, np.full(cfg["K"], 1.0 / cfg["K"]))
+
+
+def test_small_lambda_picks_the_best_sample():
+    cfg = workloads.cartpole(K=256, T=30)
+    U0 = workloads.U0_for(cfg, "random")
+    x0 = workloads.x0_for(cfg)
+    probe = dict(cfg, **{"lambda": 1e-20})
+    ref = omppi.iteration(probe, x0, U0.astype(np.float64), 0)
+    gap = np.diff(np.sort(ref["S"]))[0]
+    cfg["lambda"] = float(np.float32(gap / 2000.0))
+    ctl, ref, _, _ = run_rollout(cfg, U0=U0)
+    k = int(np.argmin(ref["S"]))
+    assert int(np.argmin(ctl.S.cpu().numpy())) == k
+    ctl.update()
+    U = ctl.U.cpu().numpy()
+    assert np.abs(U - (U0 + ref["eps"][k])).max() < U_ATOL
+    assert ctl.W.cpu().numpy()[k] == 1.0
+
+
+def test_nu_zero_is_gaussian_only_and_keeps_the_gaussian_draws():
+    cfg = workloads.cartpole(K=64, T=20, nu=0.0, debug_dump=1)
+    U0 = workloads.U0_for(cfg, "random")
+    x0 = workloads.x0_for(cfg)
+    ctl = Controller(cfg, U0)
+    ctl.rollout(x0)
+    S_ref, U_ref = omppi.gaussian_only_iteration(cfg, x0, U0.astype(np.float64), 0)
+    assert s_rel_err(ctl.S.cpu().numpy(), S_ref).max() < S_RTOL
+    zD0 = ctl.debug_draws()[0].cpu().numpy()
+    ctl2 = Controller(dict(cfg, nu=5.0), U0)
+    ctl2.rollout(x0)
+    assert np.array_equal(ctl2.debug_draws()[0].cpu().numpy(), zD0)
+
+
+def test_determinism_and_debug_variant_agree():
+    cfg = workloads.quadrotor(K=2048, T=50)
+    x0 = workloads.x0_for(cfg)
+    outs = []
+    for dbg in (0, 0, 1):
+        ctl = Controller(dict(cfg, debug_dump=dbg))
+        ctl.step(x0, 2)
+        outs.append((ctl.S.cpu().numpy(), ctl.U.cpu().numpy(), ctl.stats()))
+    for S, U, st in outs[1:]:
+        assert np.array_equal(S, outs[0][0]) and np.array_equal(U, outs[0][1])
+        assert st == outs[0][2]
+
+
+def test_shift_and_u0():
+    cfg = workloads.quadrotor(K=64, T=10)
+    U0 = workloads.U0_for(cfg, "random")
+    ctl = Controller(cfg, U0)
+    u0 = ctl.shift().cpu().numpy()
+    U = ctl.U.cpu().numpy()
+    ref_u0, ref_U = omppi.shift(U0.astype(np.float64), omppi.f32(cfg["u_init"]))
+    assert np.array_equal(u0, ref_u0.astype(np.float32))
+    assert np.array_equal(U, ref_U.astype(np.float32))
+    pinned = torch.empty(4, dtype=torch.float32, pin_memory=True)
+    ctl.shift(out=pinned)
+    torch.cuda.synchronize()
+    assert np.array_equal(pinned.numpy(), ref_U[0].astype(np.float32))
+
+
+def test_long_horizon_shift():
+    cfg = workloads.cartpole(K=64, T=3000)
+    U0 = workloads.U0_for(cfg, "random")
+    ctl = Controller(cfg, U0)
+    ctl.shift()
+    ctl.shift()
+    U = ctl.U.cpu().numpy()
+    assert np.array_equal(U[:-2], U0[2:]) and not U[-2:].any()
+
+
+def test_all_nonfinite_leaves_U_unchanged():
+    cfg = workloads.cartpole()
+    U0 = workloads.U0_for(cfg, "random")
+    ctl = Controller(cfg, U0)
+    x0 = np.full(4, np.nan, dtype=np.float32)
+    ctl.step(x0, 1)
+    st = ctl.stats()
+    assert st["status"] == native.C["MPPI_ENONFINITE"] and st["n_finite"] == 0
+    assert st["iteration"] == 1
+    assert np.array_equal(ctl.U.cpu().numpy(), U0)
+    ctl.step(workloads.x0_for(cfg), 1)
+    assert ctl.stats()["status"] == 0
+
+
+def test_partially_nonfinite_costs_are_ignored():
+    cfg = workloads.cartpole()
+    U0 = workloads.U0_for(cfg, "random")
+    x0 = workloads.x0_for(cfg)
+    ctl, ref, _, _ = run_rollout(cfg, U0=U0)
+    S = ref["S"].copy()
+    S[::3] = np.nan
+    S[1::7] = np.inf
+    w, rho, eta, st = omppi.weights(S, 1.0)
+    ctl.set_S(S)
+    st_gpu = ctl.stats()
+    assert st_gpu["n_finite"] == np.isfinite(S).sum() and st_gpu["rho"] == rho
+    assert abs(st_gpu["eta"] - eta) < 1e-12 * eta
+    assert np.allclose(ctl.W.cpu().numpy(), w, rtol=1e-12, atol=1e-300)
+    ctl.update()
+    ref_U = omppi.update(U0.astype(np.float64), w, ref["eps"])
+    assert np.abs(ctl.U.cpu().numpy() - ref_U).max() < U_ATOL
+
+
+@pytest.mark.parametrize("preset,K", [("cartpole_mpc", 4096), ("quadrotor_hover", 8192)])
+def test_full_size_sampled_parity(preset, K):
+    """Full benchmark shapes: every S_k checked on a sample of k the oracle
+    computes one by one, plus properties of the whole iteration."""
+    cfg = workloads.PRESETS[preset]()
+    assert cfg["K"] == K
+    x0 = workloads.x0_for(cfg)
+    U0 = workloads.U0_for(cfg, "random")
+    ctl = Controller(cfg, U0)
+    ctl.rollout(x0)
+    S = ctl.S.cpu().numpy()
+    idx = np.unique(np.concatenate([np.arange(0, K, K // 97), [K - 1], np.argsort(S)[:8]]))
+    ref = omppi.iteration(cfg, x0, U0.astype(np.float64), 0, k_index=idx)
+    excl = near_crash(ref)
+    err = s_rel_err(S[idx], ref["S"])[~excl]
+    assert err.max() < S_RTOL, err.max()
+    W = ctl.W.cpu().numpy()
+    assert (W >= 0).all() and abs(W.sum() - 1) < 1e-12
+    st = ctl.stats()
+    assert st["rho"] == S.min() and st["n_finite"] == K
+    eps = ctl.eps.cpu().numpy()
+    ctl.update()
+    dU = ctl.U.cpu().numpy() - U0
+    ref_dU = np.einsum("k,tjk->tj", W, eps.astype(np.float64))
+    assert np.abs(dU - ref_dU).max() < U_ATOL
+
+
+def test_plant_step_matches_the_oracle_dynamics():
+    from oracle import models
+    for preset in ("cartpole_single", "quadrotor_hover", "double_integrator"):
+        cfg = workloads.PRESETS[preset]()
+        n, m, q = native.dims(cfg["dynamics"])
+        ctl = Controller(cfg)
+        rng = np.random.default_rng(3)
+        x = workloads.x0_for(cfg).astype(np.float32) + 0.1 * rng.standard_normal(n).astype(np.float32)
+        u = np.asarray(cfg["u_init"][:m], np.float32) + rng.standard_normal(m).astype(np.float32)
+        d = rng.standard_normal(m).astype(np.float32)
+        xd = torch.tensor(x, device="cuda")
+        ctl.plant_step(xd, torch.tensor(u, device="cuda"), torch.tensor(d, device="cuda"))
+        P = omppi.f32(cfg["params"])
+        ref = models.euler_step(cfg["dynamics"], x[None].astype(np.float64),
+                                (u + d)[None].astype(np.float64), np.zeros((1, 3)),
+                                float(omppi.f32(cfg["dt"])), P)[0]
+        assert np.abs(xd.cpu().numpy() - ref).max() < 1e-5 * (1 + np.abs(ref).max())
+
+
+def test_multi_iteration_draws_follow_the_iteration_index():
+    cfg = workloads.cartpole(K=128, T=20, debug_dump=1, start_iteration=10)
+    x0 = workloads.x0_for(cfg)
+    ctl = Controller(cfg)
+    ctl.step(x0, 3)
+    assert ctl.stats()["iteration"] == 13
+    _, N, _ = ctl.debug_draws()
+    z_D, N_ref, _ = noise.sample(cfg, 12)
+    assert np.array_equal(N.cpu().numpy(), N_ref)
+
+
+def test_error_paths():
+    cfg = workloads.cartpole()
+    ctl = Controller(cfg)
+    with pytest.raises(native.MppiError) as e:
+        ctl.debug_draws()
+    assert e.value.code == native.C["MPPI_EUNSUPPORTED"]
+    with pytest.raises(native.MppiError):
+        ctl.step(workloads.x0_for(cfg), 0)
+    import ctypes
+    c = native.make_config(cfg)
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    out = ctypes.c_void_p()
+    rc = native.lib().mppi_jump_init(ctypes.byref(c), ctypes.c_void_p(ws.data_ptr()), 1024, None,
+                                      None, ctypes.byref(out))
+    assert rc == native.C["MPPI_EWORKSPACE"] and not out.value
+    big = torch.empty(native.workspace_bytes(cfg) + 512, dtype=torch.uint8, device="cuda")
+    rc = native.lib().mppi_jump_init(ctypes.byref(c), ctypes.c_void_p(big.data_ptr() + 4),
+                                      native.workspace_bytes(cfg), None, None, ctypes.byref(out))
+    assert rc == native.C["MPPI_EWORKSPACE"]
+    bad = native.make_config(dict(cfg, K=0))
+    rc = native.lib().mppi_jump_init(ctypes.byref(bad), ctypes.c_void_p(big.data_ptr()),
+                                      big.numel(), None, None, ctypes.byref(out))
+    assert rc == native.C["MPPI_EINVAL"]
+    with pytest.raises((native.MppiError, ValueError)):
+        ctl.set_S(np.zeros(cfg["K"] + 1))
