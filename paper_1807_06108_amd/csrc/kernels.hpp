@@ -52,7 +52,8 @@ struct Buffers {
   double* E;          // [K] exp(-(S_k - rho_wg)/lambda)
   WgPartial* part;    // [ceil(K/256)]
   double* scale;      // [ceil(K/256)] exp(-(rho_wg - rho)/lambda)
-  double* upart;      // [T*m][nch]
+  double* upart;      // [T*m][nch]   chunk partials of update_kernel
+  double* wpart;      // [nwg][T*m]   workgroup partials of the fused epilogue
   mppi_jump_stats* stats;
   uint32_t* counters; // [0] rollout, [1] update
   float* dbg_zD;      // [K][T][m]
@@ -111,13 +112,59 @@ __device__ __forceinline__ void stats_epilogue(const DevParams& p, const Buffers
 }
 
 // ------------------------------------------------------------------ rollout
+// Draws of one (sample, step): standard normals, the control perturbation
+// eps (plus the jump when it enters through the control channel), the
+// body-force disturbance (when it does not), and the jump count.  Branch
+// free: sqrt(0) = 0 removes a zero count's jump.
 template <int DYN, bool JUMPS>
-struct Draws {
+struct Noise {
   using Md = Model<DYN>;
   static constexpr int NN = JUMPS ? Md::M + Md::Q : Md::M;   // normals needed
   static constexpr int NW = JUMPS ? Md::COUNT_WORD + 1 : 2 * ((Md::M + 1) / 2);
   static constexpr int NB = (NW + 3) / 4;                     // Philox blocks
+  float z[NN + 1];
+  float eps[Md::M];
+  float gust[3];
+  int n;
 };
+
+template <int DYN, bool JUMPS>
+__device__ __forceinline__ void draw_noise(Noise<DYN, JUMPS>& o, const DevParams& p, uint32_t t,
+                                           uint32_t k, uint32_t it) {
+  using Md = Model<DYN>;
+  using Nz = Noise<DYN, JUMPS>;
+  uint32_t w[4 * Nz::NB];
+#pragma unroll
+  for (int blk = 0; blk < Nz::NB; ++blk) {
+    const Words4 r = philox4x32_10(t, k, it, p.ctr3 | (uint32_t)blk, p.key0, p.key1);
+    w[4 * blk + 0] = r.w0;
+    w[4 * blk + 1] = r.w1;
+    w[4 * blk + 2] = r.w2;
+    w[4 * blk + 3] = r.w3;
+  }
+#pragma unroll
+  for (int i = 0; i < Nz::NN; i += 2) {
+    if (i + 1 < Nz::NN)
+      box_muller(w[i], w[i + 1], o.z[i], o.z[i + 1]);
+    else
+      o.z[i] = box_muller_cos(w[i], w[i + 1]);
+  }
+#pragma unroll
+  for (int j = 0; j < Md::M; ++j) o.eps[j] = p.sigma[j] * o.z[j];
+  o.gust[0] = o.gust[1] = o.gust[2] = 0.f;
+  o.n = 0;
+  if constexpr (JUMPS) {
+    o.n = jump_count(w[Md::COUNT_WORD], p.th, p.n_th);
+    const float sq = __builtin_amdgcn_sqrtf((float)o.n);
+    if constexpr (Md::JUMP_IN_CONTROL) {
+#pragma unroll
+      for (int j = 0; j < Md::M; ++j) o.eps[j] += p.sigJ[j] * sq * o.z[Md::M + j];
+    } else {
+#pragma unroll
+      for (int i = 0; i < Md::Q; ++i) o.gust[i] = p.sigJ[i] * sq * o.z[Md::M + i];
+    }
+  }
+}
 
 __device__ __forceinline__ void kahan_add(float& s, float& comp, float term) {
   const float y = term - comp;
@@ -126,12 +173,95 @@ __device__ __forceinline__ void kahan_add(float& s, float& comp, float term) {
   s = t;
 }
 
-template <int DYN, bool JUMPS, bool DEBUG>
+// Fused epilogue: per-workgroup statistics of eq. (37) AND per-workgroup
+// weighted perturbation sums P[wg][r] = sum_{k in wg} exp(-(S_k - rho_wg)/lambda)
+// eps[r][k]; the last workgroup to arrive combines them with the rescale
+// exp(-(rho_wg - rho)/lambda) and applies U[r] += alpha * sum_wg ... / eta
+// (eq. (36) / (49)).  One kernel per iteration.
+__device__ __forceinline__ void fused_epilogue(const DevParams& p, const Buffers& b, double Sd,
+                                               bool active, int R) {
+  __shared__ double lds[kWaves];
+  __shared__ double e_lds[kBlock];
+  __shared__ int is_last;
+  const bool fin = active && isfinite(Sd);
+  const double rho_wg = block_min(fin ? Sd : INFINITY, lds);
+  const double e = fin ? exp(-(Sd - rho_wg) / p.lam_d) : 0.0;
+  const int k0 = blockIdx.x * kBlock;
+  if (active) b.E[k0 + threadIdx.x] = e;
+  e_lds[threadIdx.x] = e;
+  const double eta_wg = block_sum(e, lds);
+  const double nfin = block_sum(fin ? 1.0 : 0.0, lds);
+  // the workgroup's own eps tile: written above by its threads, visible
+  // after the barriers of the reductions
+  for (int r = threadIdx.x; r < R; r += kBlock) {
+    const float4* row = reinterpret_cast<const float4*>(b.eps + (size_t)r * p.Ks + k0);
+    double acc = 0.0;
+#pragma unroll 8
+    for (int j = 0; j < kBlock / 4; ++j) {
+      const float4 v = row[j];
+      acc += e_lds[4 * j] * (double)v.x;
+      acc += e_lds[4 * j + 1] * (double)v.y;
+      acc += e_lds[4 * j + 2] * (double)v.z;
+      acc += e_lds[4 * j + 3] * (double)v.w;
+    }
+    b.wpart[(size_t)blockIdx.x * R + r] = acc;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    b.part[blockIdx.x].rho = rho_wg;
+    b.part[blockIdx.x].eta = eta_wg;
+    b.part[blockIdx.x].nfin = (int32_t)nfin;
+    __threadfence();
+    const uint32_t prev = atomicAdd(&b.counters[0], 1u);
+    is_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  const int nwg = gridDim.x;
+  double m = INFINITY;
+  for (int j = threadIdx.x; j < nwg; j += kBlock)
+    if (b.part[j].nfin > 0) m = fmin(m, b.part[j].rho);
+  const double rho = block_min(m, lds);
+  double eta = 0.0, cnt = 0.0;
+  for (int j = threadIdx.x; j < nwg; j += kBlock) {
+    const WgPartial q = b.part[j];
+    const double sc = (q.nfin > 0) ? exp(-(q.rho - rho) / p.lam_d) : 0.0;
+    b.scale[j] = sc;
+    eta += q.eta * sc;
+    cnt += q.nfin;
+  }
+  eta = block_sum(eta, lds);
+  cnt = block_sum(cnt, lds);  // its barrier also publishes scale[] to the block
+  const bool ok = cnt > 0;
+  if (ok) {
+    const double f = (double)p.alpha / eta;
+    for (int r = threadIdx.x; r < R; r += kBlock) {
+      double d = 0.0;
+      for (int j = 0; j < nwg; ++j) d += b.scale[j] * b.wpart[(size_t)j * R + r];
+      b.U[r] = (float)((double)b.U[r] + f * d);
+    }
+  }
+  if (threadIdx.x == 0) {
+    const uint64_t next = b.stats->iteration + 1;
+    b.stats->rho = rho;
+    b.stats->eta = eta;
+    b.stats->n_finite = (int32_t)cnt;
+    b.stats->status = ok ? MPPI_OK : MPPI_ENONFINITE;
+    b.stats->iteration = next;
+    b.counters[0] = 0u;
+  }
+}
+
+// FORM: MPPI_COST_IT or MPPI_COST_SO.  FUSED: the epilogue also applies the
+// update (one kernel per iteration); otherwise it only forms the statistics
+// and update_kernel follows.
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED>
 __global__ __launch_bounds__(256) void rollout_kernel(const DevParams p, const Buffers b,
                                                       const float* __restrict__ x0,
-                                                      const float* __restrict__ U) {
+                                                      const float* __restrict__ U, int R) {
   using Md = Model<DYN>;
-  using D = Draws<DYN, JUMPS>;
   constexpr int N = Md::N, M = Md::M, Q = Md::Q;
   const int k = blockIdx.x * kBlock + threadIdx.x;
   const bool active = k < p.K;
@@ -143,43 +273,13 @@ __global__ __launch_bounds__(256) void rollout_kernel(const DevParams p, const B
   bool crashed = Md::CAN_CRASH ? Md::crashed(x, p.mc) : false;
   float S = 0.f, comp = 0.f;
 
+  // software pipeline: the draws of step t + 1 are formed while step t's
+  // dynamics run (they do not depend on the state)
+  Noise<DYN, JUMPS> nxt;
+  draw_noise(nxt, p, 0u, (uint32_t)k, it);
   for (int t = 0; t < p.T; ++t) {
-    uint32_t w[4 * D::NB];
-#pragma unroll
-    for (int blk = 0; blk < D::NB; ++blk) {
-      const Words4 r = philox4x32_10((uint32_t)t, (uint32_t)k, it, p.ctr3 | (uint32_t)blk,
-                                     p.key0, p.key1);
-      w[4 * blk + 0] = r.w0;
-      w[4 * blk + 1] = r.w1;
-      w[4 * blk + 2] = r.w2;
-      w[4 * blk + 3] = r.w3;
-    }
-    float z[D::NN + 1];
-#pragma unroll
-    for (int i = 0; i < D::NN; i += 2) {
-      if (i + 1 < D::NN)
-        box_muller(w[i], w[i + 1], z[i], z[i + 1]);
-      else
-        z[i] = box_muller_cos(w[i], w[i + 1]);
-    }
-    float eps[M], gust[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int j = 0; j < M; ++j) eps[j] = p.sigma[j] * z[j];
-    int ncount = 0;
-    if constexpr (JUMPS) {
-      ncount = jump_count(w[Md::COUNT_WORD], p.th, p.n_th);
-      if (ncount > 0) {
-        float sq = 1.f;
-        if (ncount > 1) sq = __builtin_amdgcn_sqrtf((float)ncount);
-        if constexpr (Md::JUMP_IN_CONTROL) {
-#pragma unroll
-          for (int j = 0; j < M; ++j) eps[j] += p.sigJ[j] * sq * z[M + j];
-        } else {
-#pragma unroll
-          for (int i = 0; i < Q; ++i) gust[i] = p.sigJ[i] * sq * z[M + i];
-        }
-      }
-    }
+    const Noise<DYN, JUMPS> cur = nxt;
+    draw_noise(nxt, p, (uint32_t)(t + 1), (uint32_t)k, it);
 
     // modified path cost, eqs. (34)-(35), on the pre-step state
     float u[M];
@@ -191,21 +291,21 @@ __global__ __launch_bounds__(256) void rollout_kernel(const DevParams p, const B
       const float d = x[i] - p.goal[i];
       qx += p.Q[i] * d * d;
     }
-    if (Md::CAN_CRASH && crashed) qx += p.pen;
+    if constexpr (Md::CAN_CRASH) qx += crashed ? p.pen : 0.f;
     float term;
-    if (p.cost_form == MPPI_COST_IT) {
+    if constexpr (FORM == MPPI_COST_IT) {
       float ctrl = 0.f, is = 0.f;
 #pragma unroll
       for (int j = 0; j < M; ++j) {
         ctrl += p.halfR[j] * u[j] * u[j];
-        is += (p.isc[j] * u[j] + p.isv[j] * eps[j]) * eps[j];
+        is += (p.isc[j] * u[j] + p.isv[j] * cur.eps[j]) * cur.eps[j];
       }
       term = (qx + ctrl) * p.dt + is;
     } else {
       float ctrl = 0.f;
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        const float v = u[j] + eps[j];
+        const float v = u[j] + cur.eps[j];
         ctrl += p.halfR[j] * v * v;
       }
       term = (qx + ctrl) * p.dt;
@@ -214,27 +314,31 @@ __global__ __launch_bounds__(256) void rollout_kernel(const DevParams p, const B
 
     float v[M];
 #pragma unroll
-    for (int j = 0; j < M; ++j) v[j] = u[j] + eps[j];
-    if (!crashed) {
-      Md::step(x, v, gust, p.dt, p.mc);
-      if (Md::CAN_CRASH) crashed = Md::crashed(x, p.mc);
+    for (int j = 0; j < M; ++j) v[j] = u[j] + cur.eps[j];
+    if constexpr (Md::CAN_CRASH) {
+      float xn[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) xn[i] = x[i];
+      Md::step(xn, v, cur.gust, p.dt, p.mc);
+#pragma unroll
+      for (int i = 0; i < N; ++i) x[i] = crashed ? x[i] : xn[i];
+      crashed = crashed || Md::crashed(x, p.mc);
+    } else {
+      Md::step(x, v, cur.gust, p.dt, p.mc);
     }
 
-    if (active) {
+    // every lane of the grid stores (rows are padded to whole workgroups);
+    // lanes past K carry zero weight
 #pragma unroll
-      for (int j = 0; j < M; ++j) b.eps[(size_t)(t * M + j) * p.Ks + k] = eps[j];
-      if constexpr (DEBUG) {
+    for (int j = 0; j < M; ++j) b.eps[(size_t)(t * M + j) * p.Ks + k] = cur.eps[j];
+    if constexpr (DEBUG) {
+      if (active) {
         const size_t kt = (size_t)k * p.T + t;
 #pragma unroll
-        for (int j = 0; j < M; ++j) b.dbg_zD[kt * M + j] = z[j];
-        b.dbg_N[kt] = ncount;
-        if constexpr (JUMPS) {
+        for (int j = 0; j < M; ++j) b.dbg_zD[kt * M + j] = cur.z[j];
+        b.dbg_N[kt] = cur.n;
 #pragma unroll
-          for (int i = 0; i < Q; ++i) b.dbg_zJ[kt * Q + i] = z[M + i];
-        } else {
-#pragma unroll
-          for (int i = 0; i < Q; ++i) b.dbg_zJ[kt * Q + i] = 0.f;
-        }
+        for (int i = 0; i < Q; ++i) b.dbg_zJ[kt * Q + i] = JUMPS ? cur.z[M + i] : 0.f;
       }
     }
   }
@@ -244,11 +348,14 @@ __global__ __launch_bounds__(256) void rollout_kernel(const DevParams p, const B
     const float d = x[i] - p.goal[i];
     qf += p.Qf[i] * d * d;
   }
-  if (Md::CAN_CRASH && crashed) qf += p.pen;
+  if constexpr (Md::CAN_CRASH) qf += crashed ? p.pen : 0.f;
   kahan_add(S, comp, qf);
   const double Sd = (double)S - (double)comp;
   if (active) b.S[k] = Sd;
-  stats_epilogue(p, b, Sd, active);
+  if constexpr (FUSED)
+    fused_epilogue(p, b, Sd, active, R);
+  else
+    stats_epilogue(p, b, Sd, active);
 }
 
 // Statistics of caller-provided costs (mppi_jump_set of S).

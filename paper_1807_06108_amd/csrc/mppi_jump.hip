@@ -144,16 +144,21 @@ int validate(const mppi_jump_config* c, int& n, int& m, int& q, std::vector<uint
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Rollouts with at most this many workgroups apply the update in their own
+// epilogue (one kernel per iteration); larger ones use update_kernel.
+constexpr int kFusedMaxWg = 512;
+
 struct Layout {
   int R, Ks, nwg, nch, chunk;
-  size_t U, eps, S, E, part, scale, upart, stats, counters, W, zD, N, zJ, total;
+  bool fused;
+  size_t U, eps, S, E, part, scale, upart, wpart, stats, counters, W, zD, N, zJ, total;
 };
 
 Layout make_layout(const mppi_jump_config* c, int m, int q) {
   Layout L{};
   const size_t K = (size_t)c->K, T = (size_t)c->T;
   L.R = (int)(T * m);
-  L.Ks = (int)align_up(K, 64);
+  L.Ks = (int)align_up(K, kBlock);  // rows padded to whole rollout workgroups
   L.nwg = (int)((K + kBlock - 1) / kBlock);
   int nch = (int)((K + 1023) / 1024);
   if (nch > 64) nch = 64;
@@ -172,6 +177,8 @@ Layout make_layout(const mppi_jump_config* c, int m, int q) {
   L.part = take((size_t)L.nwg * sizeof(WgPartial));
   L.scale = take((size_t)L.nwg * 8);
   L.upart = take((size_t)L.R * L.nch * 8);
+  L.fused = L.nwg <= kFusedMaxWg;
+  L.wpart = take(L.fused ? (size_t)L.nwg * L.R * 8 : 0);
   L.stats = take(sizeof(mppi_jump_stats));
   L.counters = take(2 * sizeof(uint32_t));
   L.W = take(K * 8);
@@ -261,26 +268,35 @@ struct mppi_jump_ctx {
 
 namespace {
 
-template <int DYN>
-int launch_rollout_dyn(mppi_jump_ctx* ctx, const float* x0, hipStream_t s) {
-  const dim3 grid(ctx->L.nwg), block(kBlock);
-  const bool jumps = ctx->p.n_th > 0, dbg = ctx->cfg.debug_dump != 0;
-  if (jumps) {
-    if (dbg)
-      rollout_kernel<DYN, true, true><<<grid, block, 0, s>>>(ctx->p, ctx->b, x0, ctx->b.U);
-    else
-      rollout_kernel<DYN, true, false><<<grid, block, 0, s>>>(ctx->p, ctx->b, x0, ctx->b.U);
-  } else {
-    if (dbg)
-      rollout_kernel<DYN, false, true><<<grid, block, 0, s>>>(ctx->p, ctx->b, x0, ctx->b.U);
-    else
-      rollout_kernel<DYN, false, false><<<grid, block, 0, s>>>(ctx->p, ctx->b, x0, ctx->b.U);
-  }
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED>
+int launch_rollout_t(mppi_jump_ctx* ctx, const float* x0, hipStream_t s) {
+  rollout_kernel<DYN, JUMPS, DEBUG, FORM, FUSED>
+      <<<dim3(ctx->L.nwg), dim3(kBlock), 0, s>>>(ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R);
   LAUNCH_CHECK("rollout_kernel");
   return MPPI_OK;
 }
 
-int launch_rollout(mppi_jump_ctx* ctx, const float* x0, hipStream_t s) {
+template <int DYN, bool JUMPS, bool DEBUG>
+int launch_rollout_form(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, bool fused) {
+  const bool it = ctx->cfg.cost_form == MPPI_COST_IT;
+  if (fused)
+    return it ? launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_IT, true>(ctx, x0, s)
+              : launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_SO, true>(ctx, x0, s);
+  return it ? launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_IT, false>(ctx, x0, s)
+            : launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_SO, false>(ctx, x0, s);
+}
+
+template <int DYN>
+int launch_rollout_dyn(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, bool fused) {
+  const bool jumps = ctx->p.n_th > 0, dbg = ctx->cfg.debug_dump != 0;
+  if (jumps)
+    return dbg ? launch_rollout_form<DYN, true, true>(ctx, x0, s, fused)
+               : launch_rollout_form<DYN, true, false>(ctx, x0, s, fused);
+  return dbg ? launch_rollout_form<DYN, false, true>(ctx, x0, s, fused)
+             : launch_rollout_form<DYN, false, false>(ctx, x0, s, fused);
+}
+
+int launch_rollout(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, bool fused) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->profiling) {
     if (ctx->events_used >= 4096) return fail(MPPI_EINVAL, "profiling buffer full (4096 launches)");
@@ -295,9 +311,9 @@ int launch_rollout(mppi_jump_ctx* ctx, const float* x0, hipStream_t s) {
   }
   int rc;
   switch (ctx->cfg.dynamics) {
-    case MPPI_DYN_LINEAR: rc = launch_rollout_dyn<MPPI_DYN_LINEAR>(ctx, x0, s); break;
-    case MPPI_DYN_CARTPOLE: rc = launch_rollout_dyn<MPPI_DYN_CARTPOLE>(ctx, x0, s); break;
-    default: rc = launch_rollout_dyn<MPPI_DYN_QUADROTOR>(ctx, x0, s); break;
+    case MPPI_DYN_LINEAR: rc = launch_rollout_dyn<MPPI_DYN_LINEAR>(ctx, x0, s, fused); break;
+    case MPPI_DYN_CARTPOLE: rc = launch_rollout_dyn<MPPI_DYN_CARTPOLE>(ctx, x0, s, fused); break;
+    default: rc = launch_rollout_dyn<MPPI_DYN_QUADROTOR>(ctx, x0, s, fused); break;
   }
   if (rc != MPPI_OK) return rc;
   if (ctx->profiling) {
@@ -400,6 +416,7 @@ int mppi_jump_init(const mppi_jump_config* cfg, void* d_workspace, size_t ws_byt
     b.part = reinterpret_cast<WgPartial*>(base + L.part);
     b.scale = reinterpret_cast<double*>(base + L.scale);
     b.upart = reinterpret_cast<double*>(base + L.upart);
+    b.wpart = L.fused ? reinterpret_cast<double*>(base + L.wpart) : nullptr;
     b.stats = reinterpret_cast<mppi_jump_stats*>(base + L.stats);
     b.counters = reinterpret_cast<uint32_t*>(base + L.counters);
     ctx->W = reinterpret_cast<double*>(base + L.W);
@@ -423,7 +440,7 @@ int mppi_jump_init(const mppi_jump_config* cfg, void* d_workspace, size_t ws_byt
 int mppi_jump_rollout(mppi_jump_ctx* ctx, const float* d_x0, void* stream) {
   return guarded([&]() -> int {
     if (!ctx || !d_x0) return fail(MPPI_EINVAL, "NULL context or state");
-    const int rc = launch_rollout(ctx, d_x0, static_cast<hipStream_t>(stream));
+    const int rc = launch_rollout(ctx, d_x0, static_cast<hipStream_t>(stream), false);
     return rc == MPPI_OK ? ok() : rc;
   });
 }
@@ -447,10 +464,12 @@ int mppi_jump_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, void* s
       return fail(MPPI_EINVAL, "iteration counter would pass 2^32");
     const hipStream_t s = static_cast<hipStream_t>(stream);
     for (int i = 0; i < iters; ++i) {
-      int rc = launch_rollout(ctx, d_x0, s);
+      int rc = launch_rollout(ctx, d_x0, s, ctx->L.fused);
       if (rc != MPPI_OK) return rc;
-      rc = launch_update(ctx, s);
-      if (rc != MPPI_OK) return rc;
+      if (!ctx->L.fused) {
+        rc = launch_update(ctx, s);
+        if (rc != MPPI_OK) return rc;
+      }
       ctx->host_iteration += 1;
     }
     return ok();
