@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--workload", default="cartpole_mpc",
                     choices=["cartpole_mpc", "cartpole_single", "quadrotor_hover"])
     ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--schedule", default="auto", choices=["auto", "lane", "ws"],
+                    help="rollout schedule (identical results)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     args = ap.parse_args()
@@ -93,6 +95,7 @@ def main():
 
     torch.cuda.set_device(0)
     cfg = workloads.PRESETS[args.workload]()
+    cfg["schedule"] = {"auto": 0, "lane": 1, "ws": 2}[args.schedule]
     iters = args.iters or (5 if args.workload == "cartpole_mpc" else 1)
     K, T = cfg["K"], cfg["T"]
     n, m = len(workloads.x0_for(cfg)), workloads.DIMS[cfg["dynamics"]][1]
@@ -151,7 +154,7 @@ def main():
         "data": "synthetic (seeded Philox draws; seeded plant disturbances)",
         "config": {"workload": args.workload, "K": K, "T": T, "dt": cfg["dt"],
                    "iters_per_control_step": iters, "dynamics": cfg["dynamics"],
-                   "nu": cfg["nu"], "form": "plain"},
+                   "nu": cfg["nu"], "form": "plain", "schedule": args.schedule},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "what": "device time per control step (iters + shift + plant)"},
         "roofline": {"bound": "alu", "kernel": "rollout_kernel",

@@ -70,6 +70,16 @@ extern "C" {
 #define MPPI_COST_IT 0
 #define MPPI_COST_SO 1
 
+/* rollout schedules (identical results, different parallel decomposition):
+ * one sample per lane, 256 samples per workgroup; or wave-specialised, 64
+ * samples per workgroup of 4 wavefronts (3 draw noise, 1 runs the state
+ * recursion), for latency when K does not fill the GPU.  AUTO picks
+ * wave-specialised for K <= MPPI_JUMP_WS_MAX_K. */
+#define MPPI_SCHED_AUTO 0
+#define MPPI_SCHED_LANE 1
+#define MPPI_SCHED_WAVE_SPECIALISED 2
+#define MPPI_JUMP_WS_MAX_K 131072
+
 /* items of mppi_jump_get / mppi_jump_set */
 #define MPPI_ITEM_U 0        /* float [T][m]                        get, set */
 #define MPPI_ITEM_S 1        /* double [K] path costs S~_k          get, set */
@@ -108,7 +118,7 @@ typedef struct mppi_jump_config {
   float x_goal[12];      /* target state x*                                    */
   float params[12];      /* dynamics constants (see below)                     */
   float crash_penalty;   /* quadrotor crash indicator weight                   */
-  int32_t reserved;      /* must be 0                                          */
+  int32_t schedule;      /* MPPI_SCHED_*: rollout work split (same results)    */
   uint64_t seed;         /* Philox key                                         */
   uint64_t controller_id;/* < 2^24; part of the Philox counter                 */
   uint64_t start_iteration; /* iteration index of the first step, < 2^32      */

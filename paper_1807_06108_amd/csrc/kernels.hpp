@@ -32,6 +32,7 @@ struct alignas(128) WgPartial {
 
 struct DevParams {
   int K, T, Ks, n_th;
+  int wg_shift;               // log2 of the samples per rollout workgroup
   uint32_t key0, key1, ctr3;  // ctr3 = controller_id << 8
   int cost_form;
   float dt, lam, alpha, pen;
@@ -53,7 +54,7 @@ struct Buffers {
   WgPartial* part;    // [ceil(K/256)]
   double* scale;      // [ceil(K/256)] exp(-(rho_wg - rho)/lambda)
   double* upart;      // [T*m][nch]   chunk partials of update_kernel
-  double* wpart;      // [nwg][T*m]   workgroup partials of the fused epilogue
+  double* wpart;      // [T*m][nwg]   workgroup partials of the fused epilogue
   mppi_jump_stats* stats;
   uint32_t* counters; // [0] rollout, [1] update
   float* dbg_zD;      // [K][T][m]
@@ -61,52 +62,159 @@ struct Buffers {
   float* dbg_zJ;      // [K][T][q]
 };
 
+// Per-sample-step constants of the rollout, staged in LDS at kernel start
+// (by the first 16 threads of any workgroup of at least 64 threads).
+// Read with wavefront-uniform addresses they land in vector registers, which
+// keeps the scalar register file free for the Philox key schedule and the
+// loop state (the 12-state model otherwise spills scalar registers).
+struct Consts {
+  float Q[12], goal[12];
+  ModelConsts mc;
+  float sigma[4], sigJ[4], isc[4], isv[4], halfR[4];
+  uint32_t th[8];
+};
+
+__device__ __forceinline__ void stage_consts(Consts& cs, const DevParams& p) {
+  const int i = threadIdx.x;
+  if (i < 12) {
+    cs.Q[i] = p.Q[i];
+    cs.goal[i] = p.goal[i];
+  }
+  if (i < 16) cs.mc.c[i] = p.mc.c[i];
+  if (i < 4) {
+    cs.sigma[i] = p.sigma[i];
+    cs.sigJ[i] = p.sigJ[i];
+    cs.isc[i] = p.isc[i];
+    cs.isv[i] = p.isv[i];
+    cs.halfR[i] = p.halfR[i];
+  }
+  if (i < 8) cs.th[i] = p.th[i];
+  __syncthreads();
+}
+
 // ------------------------------------------------------------------ epilogue
-// Per-workgroup statistics of eq. (37) for the 256 samples of this
-// workgroup, then the combine by the last workgroup to arrive.
-__device__ __forceinline__ void stats_epilogue(const DevParams& p, const Buffers& b, double Sd,
-                                               bool active) {
-  __shared__ double lds[kWaves];
+// Rollouts with at most this many workgroups apply the update in their own
+// epilogue (one kernel per iteration); larger ones use update_kernel.
+constexpr int kFusedMaxWg = 512;
+constexpr int kStageRows = 1024;  // partial rows staged in LDS per pass
+
+// Rollout epilogue over the SPW samples of this workgroup (threads below SPW
+// hold a cost; the others pass active = false):
+//   * statistics of eq. (37): rho_wg = min of the finite S_k, E_k =
+//     exp(-(S_k - rho_wg)/lambda), eta_wg = sum E_k, count of finite S_k;
+//   * FUSED: the weighted perturbation sums P[r][wg] = sum_k E_k eps[r][k]
+//     over the workgroup's own eps tile;
+//   * the last workgroup to arrive combines the partials in index order with
+//     the rescale exp(-(rho_wg - rho)/lambda) and, when FUSED, applies
+//     U[r] += alpha * sum_wg scale_wg P[r][wg] / eta (eqs. (36) / (49)) and
+//     advances the iteration counter.
+// Publication: every global partial is stored by wavefront 0, which then
+// issues the workgroup's single device-scope release fence before the
+// arrival counter is incremented (a device-scope fence writes back the L2 of
+// this XCD, so one per workgroup instead of one per wavefront).
+template <int SPW, bool FUSED, int NT = kBlock>
+__device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffers& b, double Sd,
+                                                 bool active, int R) {
+  constexpr int NW = NT / 64;
+  __shared__ double lds[NW];
+  __shared__ double e_lds[SPW];
+  __shared__ double stage[FUSED ? kStageRows : 1];
+  __shared__ double sc_lds[FUSED ? kFusedMaxWg : 1];
   __shared__ int is_last;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool fin = active && isfinite(Sd);
-  const double s = fin ? Sd : INFINITY;
-  const double rho_wg = block_min(s, lds);
+  const double rho_wg = block_min<NW>(fin ? Sd : INFINITY, lds);
   const double e = fin ? exp(-(Sd - rho_wg) / p.lam_d) : 0.0;
-  const int k = blockIdx.x * kBlock + threadIdx.x;
-  if (active) b.E[k] = e;
-  const double eta_wg = block_sum(e, lds);
-  const double nfin = block_sum(fin ? 1.0 : 0.0, lds);
-  if (threadIdx.x == 0) {
-    b.part[blockIdx.x].rho = rho_wg;
-    b.part[blockIdx.x].eta = eta_wg;
-    b.part[blockIdx.x].nfin = (int32_t)nfin;
+  const int k0 = blockIdx.x * SPW;
+  const int nwg = gridDim.x;
+  if (active) b.E[k0 + threadIdx.x] = e;
+  if (threadIdx.x < SPW) e_lds[threadIdx.x] = e;
+  const double eta_wg = block_sum<NW>(e, lds);
+  const double nfin = block_sum<NW>(fin ? 1.0 : 0.0, lds);
+  if constexpr (FUSED) {
+    // the workgroup's own eps tile (written earlier in this kernel by its
+    // threads, visible after the barriers of the reductions), reduced by all
+    // threads into LDS, stored by wavefront 0
+    for (int base = 0; base < R; base += kStageRows) {
+      const int nrow = min(kStageRows, R - base);
+      for (int i = threadIdx.x; i < nrow; i += NT) {
+        const float4* row =
+            reinterpret_cast<const float4*>(b.eps + (size_t)(base + i) * p.Ks + k0);
+        double acc = 0.0;
+#pragma unroll 8
+        for (int j = 0; j < SPW / 4; ++j) {
+          const float4 v = row[j];
+          acc += e_lds[4 * j] * (double)v.x;
+          acc += e_lds[4 * j + 1] * (double)v.y;
+          acc += e_lds[4 * j + 2] * (double)v.z;
+          acc += e_lds[4 * j + 3] * (double)v.w;
+        }
+        stage[i] = acc;
+      }
+      __syncthreads();
+      if (wave == 0)
+        for (int i = lane; i < nrow; i += 64) b.wpart[(size_t)(base + i) * nwg + blockIdx.x] = stage[i];
+      __syncthreads();
+    }
+  }
+  if (wave == 0) {
+    if (lane == 0) {
+      b.part[blockIdx.x].rho = rho_wg;
+      b.part[blockIdx.x].eta = eta_wg;
+      b.part[blockIdx.x].nfin = (int32_t)nfin;
+    }
     __threadfence();
-    const uint32_t prev = atomicAdd(&b.counters[0], 1u);
-    is_last = (prev == gridDim.x - 1);
+    if (lane == 0) {
+      const uint32_t prev = atomicAdd(&b.counters[0], 1u);
+      is_last = (prev == gridDim.x - 1);
+    }
   }
   __syncthreads();
   if (!is_last) return;
   __threadfence();
-  const int nwg = gridDim.x;
   double m = INFINITY;
-  for (int j = threadIdx.x; j < nwg; j += kBlock)
+  for (int j = threadIdx.x; j < nwg; j += NT)
     if (b.part[j].nfin > 0) m = fmin(m, b.part[j].rho);
-  const double rho = block_min(m, lds);
+  const double rho = block_min<NW>(m, lds);
   double eta = 0.0, cnt = 0.0;
-  for (int j = threadIdx.x; j < nwg; j += kBlock) {
+  for (int j = threadIdx.x; j < nwg; j += NT) {
     const WgPartial q = b.part[j];
     const double sc = (q.nfin > 0) ? exp(-(q.rho - rho) / p.lam_d) : 0.0;
     b.scale[j] = sc;
+    if constexpr (FUSED) sc_lds[j] = sc;
     eta += q.eta * sc;
     cnt += q.nfin;
   }
-  eta = block_sum(eta, lds);
-  cnt = block_sum(cnt, lds);
+  eta = block_sum<NW>(eta, lds);
+  cnt = block_sum<NW>(cnt, lds);  // its barrier also publishes sc_lds to the block
+  const bool ok = cnt > 0;
+  if constexpr (FUSED) {
+    // one thread per row; four independent accumulators keep loads in
+    // flight; the summation order is fixed
+    if (ok) {
+      const double f = (double)p.alpha / eta;
+      for (int r = threadIdx.x; r < R; r += NT) {
+        const double* wr = b.wpart + (size_t)r * nwg;
+        double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+        int j = 0;
+#pragma unroll 4
+        for (; j + 4 <= nwg; j += 4) {
+          d0 += sc_lds[j] * wr[j];
+          d1 += sc_lds[j + 1] * wr[j + 1];
+          d2 += sc_lds[j + 2] * wr[j + 2];
+          d3 += sc_lds[j + 3] * wr[j + 3];
+        }
+        for (; j < nwg; ++j) d0 += sc_lds[j] * wr[j];
+        b.U[r] = (float)((double)b.U[r] + f * ((d0 + d1) + (d2 + d3)));
+      }
+    }
+  }
   if (threadIdx.x == 0) {
     b.stats->rho = rho;
     b.stats->eta = eta;
     b.stats->n_finite = (int32_t)cnt;
-    b.stats->status = cnt > 0 ? MPPI_OK : MPPI_ENONFINITE;
+    b.stats->status = ok ? MPPI_OK : MPPI_ENONFINITE;
+    if constexpr (FUSED) b.stats->iteration = b.stats->iteration + 1;
     b.counters[0] = 0u;
   }
 }
@@ -129,8 +237,8 @@ struct Noise {
 };
 
 template <int DYN, bool JUMPS>
-__device__ __forceinline__ void draw_noise(Noise<DYN, JUMPS>& o, const DevParams& p, uint32_t t,
-                                           uint32_t k, uint32_t it) {
+__device__ __forceinline__ void draw_noise(Noise<DYN, JUMPS>& o, const DevParams& p,
+                                           const Consts& cs, uint32_t t, uint32_t k, uint32_t it) {
   using Md = Model<DYN>;
   using Nz = Noise<DYN, JUMPS>;
   uint32_t w[4 * Nz::NB];
@@ -150,18 +258,18 @@ __device__ __forceinline__ void draw_noise(Noise<DYN, JUMPS>& o, const DevParams
       o.z[i] = box_muller_cos(w[i], w[i + 1]);
   }
 #pragma unroll
-  for (int j = 0; j < Md::M; ++j) o.eps[j] = p.sigma[j] * o.z[j];
+  for (int j = 0; j < Md::M; ++j) o.eps[j] = cs.sigma[j] * o.z[j];
   o.gust[0] = o.gust[1] = o.gust[2] = 0.f;
   o.n = 0;
   if constexpr (JUMPS) {
-    o.n = jump_count(w[Md::COUNT_WORD], p.th, p.n_th);
+    o.n = jump_count(w[Md::COUNT_WORD], cs.th, p.th, p.n_th);
     const float sq = __builtin_amdgcn_sqrtf((float)o.n);
     if constexpr (Md::JUMP_IN_CONTROL) {
 #pragma unroll
-      for (int j = 0; j < Md::M; ++j) o.eps[j] += p.sigJ[j] * sq * o.z[Md::M + j];
+      for (int j = 0; j < Md::M; ++j) o.eps[j] += cs.sigJ[j] * sq * o.z[Md::M + j];
     } else {
 #pragma unroll
-      for (int i = 0; i < Md::Q; ++i) o.gust[i] = p.sigJ[i] * sq * o.z[Md::M + i];
+      for (int i = 0; i < Md::Q; ++i) o.gust[i] = cs.sigJ[i] * sq * o.z[Md::M + i];
     }
   }
 }
@@ -173,84 +281,28 @@ __device__ __forceinline__ void kahan_add(float& s, float& comp, float term) {
   s = t;
 }
 
-// Fused epilogue: per-workgroup statistics of eq. (37) AND per-workgroup
-// weighted perturbation sums P[wg][r] = sum_{k in wg} exp(-(S_k - rho_wg)/lambda)
-// eps[r][k]; the last workgroup to arrive combines them with the rescale
-// exp(-(rho_wg - rho)/lambda) and applies U[r] += alpha * sum_wg ... / eta
-// (eq. (36) / (49)).  One kernel per iteration.
-__device__ __forceinline__ void fused_epilogue(const DevParams& p, const Buffers& b, double Sd,
-                                               bool active, int R) {
-  __shared__ double lds[kWaves];
-  __shared__ double e_lds[kBlock];
-  __shared__ int is_last;
-  const bool fin = active && isfinite(Sd);
-  const double rho_wg = block_min(fin ? Sd : INFINITY, lds);
-  const double e = fin ? exp(-(Sd - rho_wg) / p.lam_d) : 0.0;
-  const int k0 = blockIdx.x * kBlock;
-  if (active) b.E[k0 + threadIdx.x] = e;
-  e_lds[threadIdx.x] = e;
-  const double eta_wg = block_sum(e, lds);
-  const double nfin = block_sum(fin ? 1.0 : 0.0, lds);
-  // the workgroup's own eps tile: written above by its threads, visible
-  // after the barriers of the reductions
-  for (int r = threadIdx.x; r < R; r += kBlock) {
-    const float4* row = reinterpret_cast<const float4*>(b.eps + (size_t)r * p.Ks + k0);
-    double acc = 0.0;
-#pragma unroll 8
-    for (int j = 0; j < kBlock / 4; ++j) {
-      const float4 v = row[j];
-      acc += e_lds[4 * j] * (double)v.x;
-      acc += e_lds[4 * j + 1] * (double)v.y;
-      acc += e_lds[4 * j + 2] * (double)v.z;
-      acc += e_lds[4 * j + 3] * (double)v.w;
+// State-free part of the stage cost of eqs. (34)-(35): nominal control cost
+// times dt plus the importance-sampling terms (IT form), or the control cost
+// of the applied control times dt (SO form).
+template <int M, int FORM>
+__device__ __forceinline__ float state_free_cost(const DevParams& p, const Consts& cs,
+                                                 const float* u, const float* eps) {
+  if constexpr (FORM == MPPI_COST_IT) {
+    float ctrl = 0.f, is = 0.f;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      ctrl += cs.halfR[j] * u[j] * u[j];
+      is += (cs.isc[j] * u[j] + cs.isv[j] * eps[j]) * eps[j];
     }
-    b.wpart[(size_t)blockIdx.x * R + r] = acc;
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    b.part[blockIdx.x].rho = rho_wg;
-    b.part[blockIdx.x].eta = eta_wg;
-    b.part[blockIdx.x].nfin = (int32_t)nfin;
-    __threadfence();
-    const uint32_t prev = atomicAdd(&b.counters[0], 1u);
-    is_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  const int nwg = gridDim.x;
-  double m = INFINITY;
-  for (int j = threadIdx.x; j < nwg; j += kBlock)
-    if (b.part[j].nfin > 0) m = fmin(m, b.part[j].rho);
-  const double rho = block_min(m, lds);
-  double eta = 0.0, cnt = 0.0;
-  for (int j = threadIdx.x; j < nwg; j += kBlock) {
-    const WgPartial q = b.part[j];
-    const double sc = (q.nfin > 0) ? exp(-(q.rho - rho) / p.lam_d) : 0.0;
-    b.scale[j] = sc;
-    eta += q.eta * sc;
-    cnt += q.nfin;
-  }
-  eta = block_sum(eta, lds);
-  cnt = block_sum(cnt, lds);  // its barrier also publishes scale[] to the block
-  const bool ok = cnt > 0;
-  if (ok) {
-    const double f = (double)p.alpha / eta;
-    for (int r = threadIdx.x; r < R; r += kBlock) {
-      double d = 0.0;
-      for (int j = 0; j < nwg; ++j) d += b.scale[j] * b.wpart[(size_t)j * R + r];
-      b.U[r] = (float)((double)b.U[r] + f * d);
+    return ctrl * p.dt + is;
+  } else {
+    float ctrl = 0.f;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const float v = u[j] + eps[j];
+      ctrl += cs.halfR[j] * v * v;
     }
-  }
-  if (threadIdx.x == 0) {
-    const uint64_t next = b.stats->iteration + 1;
-    b.stats->rho = rho;
-    b.stats->eta = eta;
-    b.stats->n_finite = (int32_t)cnt;
-    b.stats->status = ok ? MPPI_OK : MPPI_ENONFINITE;
-    b.stats->iteration = next;
-    b.counters[0] = 0u;
+    return ctrl * p.dt;
   }
 }
 
@@ -266,20 +318,22 @@ __global__ __launch_bounds__(256) void rollout_kernel(const DevParams p, const B
   const int k = blockIdx.x * kBlock + threadIdx.x;
   const bool active = k < p.K;
   const uint32_t it = (uint32_t)b.stats->iteration;
+  __shared__ Consts cs;
+  stage_consts(cs, p);
 
   float x[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) x[i] = x0[i];
-  bool crashed = Md::CAN_CRASH ? Md::crashed(x, p.mc) : false;
+  bool crashed = Md::CAN_CRASH ? Md::crashed(x, cs.mc) : false;
   float S = 0.f, comp = 0.f;
 
   // software pipeline: the draws of step t + 1 are formed while step t's
   // dynamics run (they do not depend on the state)
   Noise<DYN, JUMPS> nxt;
-  draw_noise(nxt, p, 0u, (uint32_t)k, it);
+  draw_noise(nxt, p, cs, 0u, (uint32_t)k, it);
   for (int t = 0; t < p.T; ++t) {
     const Noise<DYN, JUMPS> cur = nxt;
-    draw_noise(nxt, p, (uint32_t)(t + 1), (uint32_t)k, it);
+    draw_noise(nxt, p, cs, (uint32_t)(t + 1), (uint32_t)k, it);
 
     // modified path cost, eqs. (34)-(35), on the pre-step state
     float u[M];
@@ -288,28 +342,11 @@ __global__ __launch_bounds__(256) void rollout_kernel(const DevParams p, const B
     float qx = 0.f;
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      const float d = x[i] - p.goal[i];
-      qx += p.Q[i] * d * d;
+      const float d = x[i] - cs.goal[i];
+      qx += cs.Q[i] * d * d;
     }
     if constexpr (Md::CAN_CRASH) qx += crashed ? p.pen : 0.f;
-    float term;
-    if constexpr (FORM == MPPI_COST_IT) {
-      float ctrl = 0.f, is = 0.f;
-#pragma unroll
-      for (int j = 0; j < M; ++j) {
-        ctrl += p.halfR[j] * u[j] * u[j];
-        is += (p.isc[j] * u[j] + p.isv[j] * cur.eps[j]) * cur.eps[j];
-      }
-      term = (qx + ctrl) * p.dt + is;
-    } else {
-      float ctrl = 0.f;
-#pragma unroll
-      for (int j = 0; j < M; ++j) {
-        const float v = u[j] + cur.eps[j];
-        ctrl += p.halfR[j] * v * v;
-      }
-      term = (qx + ctrl) * p.dt;
-    }
+    const float term = qx * p.dt + state_free_cost<M, FORM>(p, cs, u, cur.eps);
     kahan_add(S, comp, term);
 
     float v[M];
@@ -319,12 +356,12 @@ __global__ __launch_bounds__(256) void rollout_kernel(const DevParams p, const B
       float xn[N];
 #pragma unroll
       for (int i = 0; i < N; ++i) xn[i] = x[i];
-      Md::step(xn, v, cur.gust, p.dt, p.mc);
+      Md::step(xn, v, cur.gust, p.dt, cs.mc);
 #pragma unroll
       for (int i = 0; i < N; ++i) x[i] = crashed ? x[i] : xn[i];
-      crashed = crashed || Md::crashed(x, p.mc);
+      crashed = crashed || Md::crashed(x, cs.mc);
     } else {
-      Md::step(x, v, cur.gust, p.dt, p.mc);
+      Md::step(x, v, cur.gust, p.dt, cs.mc);
     }
 
     // every lane of the grid stores (rows are padded to whole workgroups);
@@ -345,25 +382,24 @@ __global__ __launch_bounds__(256) void rollout_kernel(const DevParams p, const B
   float qf = 0.f;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    const float d = x[i] - p.goal[i];
+    const float d = x[i] - cs.goal[i];
     qf += p.Qf[i] * d * d;
   }
   if constexpr (Md::CAN_CRASH) qf += crashed ? p.pen : 0.f;
   kahan_add(S, comp, qf);
   const double Sd = (double)S - (double)comp;
   if (active) b.S[k] = Sd;
-  if constexpr (FUSED)
-    fused_epilogue(p, b, Sd, active, R);
-  else
-    stats_epilogue(p, b, Sd, active);
+  rollout_epilogue<kBlock, FUSED>(p, b, Sd, active, R);
 }
 
-// Statistics of caller-provided costs (mppi_jump_set of S).
+// Statistics of caller-provided costs (mppi_jump_set of S), with the
+// workgroup size of the context's rollout schedule.
+template <int SPW>
 __global__ __launch_bounds__(256) void restats_kernel(const DevParams p, const Buffers b) {
-  const int k = blockIdx.x * kBlock + threadIdx.x;
-  const bool active = k < p.K;
+  const int k = blockIdx.x * SPW + threadIdx.x;
+  const bool active = threadIdx.x < SPW && k < p.K;
   const double Sd = active ? b.S[k] : 0.0;
-  stats_epilogue(p, b, Sd, active);
+  rollout_epilogue<SPW, false>(p, b, Sd, active, 0);
 }
 
 // ------------------------------------------------------------------ update
@@ -382,7 +418,7 @@ __global__ __launch_bounds__(256) void update_kernel(const DevParams p, const Bu
     for (int rr = 0; rr < kRowsPerWg; ++rr) acc[rr] = 0.0;
     const int kend = min(p.K, (c + 1) * chunk);
     for (int k = c * chunk + threadIdx.x; k < kend; k += kBlock) {
-      const double e = b.E[k] * b.scale[k >> 8];
+      const double e = b.E[k] * b.scale[k >> p.wg_shift];
 #pragma unroll
       for (int rr = 0; rr < kRowsPerWg; ++rr)
         if (r0 + rr < R) acc[rr] += e * (double)b.eps[(size_t)(r0 + rr) * p.Ks + k];
@@ -476,7 +512,7 @@ __global__ void weights_kernel(const DevParams p, const Buffers b, double* __res
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= p.K) return;
   const mppi_jump_stats st = *b.stats;
-  W[k] = st.status == MPPI_OK ? b.E[k] * b.scale[k >> 8] / st.eta : 0.0;
+  W[k] = st.status == MPPI_OK ? b.E[k] * b.scale[k >> p.wg_shift] / st.eta : 0.0;
 }
 
 __global__ void philox_kernel(const uint32_t* __restrict__ ctr, uint32_t k0, uint32_t k1,
@@ -491,3 +527,5 @@ __global__ void philox_kernel(const uint32_t* __restrict__ ctr, uint32_t k0, uin
 }
 
 }  // namespace mppi
+
+#include "rollout_ws.hpp"

@@ -109,7 +109,8 @@ int validate(const mppi_jump_config* c, int& n, int& m, int& q, std::vector<uint
   if (c->cost_form != MPPI_COST_IT && c->cost_form != MPPI_COST_SO)
     return fail(MPPI_EINVAL, "unknown cost_form %d", c->cost_form);
   if (c->debug_dump != 0 && c->debug_dump != 1) return fail(MPPI_EINVAL, "debug_dump must be 0 or 1");
-  if (c->reserved != 0) return fail(MPPI_EINVAL, "reserved must be 0");
+  if (c->schedule < MPPI_SCHED_AUTO || c->schedule > MPPI_SCHED_WAVE_SPECIALISED)
+    return fail(MPPI_EINVAL, "unknown schedule %d", c->schedule);
   for (int j = 0; j < m; ++j)
     if (!(std::isfinite(c->sigma[j]) && c->sigma[j] >= 0.f))
       return fail(MPPI_EINVAL, "sigma[%d] must be finite and >= 0", j);
@@ -144,12 +145,10 @@ int validate(const mppi_jump_config* c, int& n, int& m, int& q, std::vector<uint
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// Rollouts with at most this many workgroups apply the update in their own
-// epilogue (one kernel per iteration); larger ones use update_kernel.
-constexpr int kFusedMaxWg = 512;
-
 struct Layout {
   int R, Ks, nwg, nch, chunk;
+  bool ws;     // wave-specialised schedule (64 samples per workgroup)
+  int spw;     // samples per rollout workgroup
   bool fused;
   size_t U, eps, S, E, part, scale, upart, wpart, stats, counters, W, zD, N, zJ, total;
 };
@@ -158,8 +157,11 @@ Layout make_layout(const mppi_jump_config* c, int m, int q) {
   Layout L{};
   const size_t K = (size_t)c->K, T = (size_t)c->T;
   L.R = (int)(T * m);
+  L.ws = c->schedule == MPPI_SCHED_WAVE_SPECIALISED ||
+         (c->schedule == MPPI_SCHED_AUTO && c->K <= MPPI_JUMP_WS_MAX_K);
+  L.spw = L.ws ? kWsSamples : kBlock;
   L.Ks = (int)align_up(K, kBlock);  // rows padded to whole rollout workgroups
-  L.nwg = (int)((K + kBlock - 1) / kBlock);
+  L.nwg = (int)((K + L.spw - 1) / L.spw);
   int nch = (int)((K + 1023) / 1024);
   if (nch > 64) nch = 64;
   L.chunk = (int)align_up((K + nch - 1) / nch, kBlock);
@@ -198,6 +200,7 @@ DevParams make_params(const mppi_jump_config* c, int n, int m, int q, const Layo
   p.K = c->K;
   p.T = c->T;
   p.Ks = L.Ks;
+  p.wg_shift = L.ws ? 6 : 8;
   p.key0 = (uint32_t)(c->seed & 0xFFFFFFFFull);
   p.key1 = (uint32_t)(c->seed >> 32);
   p.ctr3 = (uint32_t)(c->controller_id << 8);
@@ -270,9 +273,15 @@ namespace {
 
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED>
 int launch_rollout_t(mppi_jump_ctx* ctx, const float* x0, hipStream_t s) {
-  rollout_kernel<DYN, JUMPS, DEBUG, FORM, FUSED>
-      <<<dim3(ctx->L.nwg), dim3(kBlock), 0, s>>>(ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R);
-  LAUNCH_CHECK("rollout_kernel");
+  if (ctx->L.ws) {
+    rollout_ws_kernel<DYN, JUMPS, DEBUG, FORM, FUSED><<<dim3(ctx->L.nwg), dim3(64 * WsWaves<DYN>::W),
+                                                       0, s>>>(ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R);
+    LAUNCH_CHECK("rollout_ws_kernel");
+  } else {
+    rollout_kernel<DYN, JUMPS, DEBUG, FORM, FUSED>
+        <<<dim3(ctx->L.nwg), dim3(kBlock), 0, s>>>(ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R);
+    LAUNCH_CHECK("rollout_kernel");
+  }
   return MPPI_OK;
 }
 
@@ -548,7 +557,10 @@ int mppi_jump_set(mppi_jump_ctx* ctx, int32_t what, const void* src, size_t src_
       const size_t bytes = (size_t)ctx->cfg.K * 8;
       if (src_bytes != bytes) return fail(MPPI_EINVAL, "S needs %zu bytes, got %zu", bytes, src_bytes);
       HIP_TRY(hipMemcpyAsync(ctx->b.S, src, bytes, hipMemcpyDefault, s));
-      restats_kernel<<<ctx->L.nwg, kBlock, 0, s>>>(ctx->p, ctx->b);
+      if (ctx->L.ws)
+        restats_kernel<kWsSamples><<<ctx->L.nwg, kBlock, 0, s>>>(ctx->p, ctx->b);
+      else
+        restats_kernel<kBlock><<<ctx->L.nwg, kBlock, 0, s>>>(ctx->p, ctx->b);
       LAUNCH_CHECK("restats_kernel");
       return ok();
     }

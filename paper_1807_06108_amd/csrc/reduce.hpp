@@ -21,8 +21,9 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Workgroup reductions: every thread gets the result.  `lds` holds kWaves
-// doubles; a __syncthreads() separates consecutive uses of the same buffer.
+// Workgroup reductions over NW wavefronts: every thread gets the result.
+// `lds` holds NW doubles; a __syncthreads() separates consecutive uses.
+template <int NW = kWaves>
 __device__ __forceinline__ double block_min(double v, double* lds) {
   v = wave_min(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -30,11 +31,12 @@ __device__ __forceinline__ double block_min(double v, double* lds) {
   __syncthreads();
   double r = lds[0];
 #pragma unroll
-  for (int w = 1; w < kWaves; ++w) r = fmin(r, lds[w]);
+  for (int w = 1; w < NW; ++w) r = fmin(r, lds[w]);
   __syncthreads();
   return r;
 }
 
+template <int NW = kWaves>
 __device__ __forceinline__ double block_sum(double v, double* lds) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -42,7 +44,7 @@ __device__ __forceinline__ double block_sum(double v, double* lds) {
   __syncthreads();
   double r = lds[0];
 #pragma unroll
-  for (int w = 1; w < kWaves; ++w) r += lds[w];
+  for (int w = 1; w < NW; ++w) r += lds[w];
   __syncthreads();
   return r;
 }

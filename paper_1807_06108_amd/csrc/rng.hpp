@@ -66,13 +66,14 @@ __device__ __forceinline__ float box_muller_cos(uint32_t wr, uint32_t wa) {
 }
 
 // Jump count by inversion: the number of thresholds the word reaches.  The
-// first eight thresholds are compared unrolled (their values stay in scalar
-// registers across the time loop); longer tables continue in a loop.
-__device__ __forceinline__ int jump_count(uint32_t w, const uint32_t* th, int n_th) {
+// first eight thresholds come from th8 (kept in vector registers by the
+// callers), longer tables continue from th_all in a loop.
+__device__ __forceinline__ int jump_count(uint32_t w, const uint32_t* th8,
+                                          const uint32_t* th_all, int n_th) {
   int n = 0;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) n += (j < n_th && w >= th[j]) ? 1 : 0;
-  for (int j = 8; j < n_th; ++j) n += (w >= th[j]) ? 1 : 0;
+  for (int j = 0; j < 8; ++j) n += (j < n_th && w >= th8[j]) ? 1 : 0;
+  for (int j = 8; j < n_th; ++j) n += (w >= th_all[j]) ? 1 : 0;
   return n;
 }
 

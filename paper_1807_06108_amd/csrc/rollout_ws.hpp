@@ -1,0 +1,174 @@
+// Wave-specialised rollout: a workgroup of W wavefronts serves 64 samples.
+// W - 1 producer waves form the draws (Philox, Box-Muller,
+// jump counts), the applied controls v = U[t] + eps and the state-free part of
+// the stage cost for a chunk of time steps and pass them through an LDS ring;
+// the consumer wave runs the state recursion (dynamics and state cost) of
+// the previous chunk meanwhile.  The per-step instruction stream of the
+// serial recursion then holds only the dynamics and the state cost, which
+// is what bounds the iteration latency when K is too small to fill the chip.
+// Results are identical to the one-sample-per-lane rollout: the same draws
+// from the same counters and the same fp32 arithmetic in the same order.
+#pragma once
+#include "kernels.hpp"
+
+namespace mppi {
+
+constexpr int kWsSamples = 64;  // samples per workgroup
+constexpr int kWsChunk = 16;    // time steps per ring slot
+
+// Wavefronts per workgroup: two per SIMD for the light models, so that a
+// producer shares each SIMD with another wave and latency is hidden; one per
+// SIMD for the 12-state model, whose consumer needs the larger register file.
+template <int DYN>
+struct WsWaves {
+  static constexpr int W = DYN == MPPI_DYN_QUADROTOR ? 4 : 8;
+};
+
+template <int DYN>
+struct WsRing {
+  using Md = Model<DYN>;
+  static constexpr int NG = Md::JUMP_IN_CONTROL ? 0 : 3;  // disturbance floats
+  static constexpr int NF = Md::M + NG + 1;               // v[M], gust[NG], state-free cost
+};
+
+template <int DYN, bool JUMPS, bool DEBUG, int FORM>
+__device__ __forceinline__ void ws_produce(const DevParams& p, const Consts& cs, const Buffers& b,
+                                           const float* __restrict__ U, float* slot, int t,
+                                           int k, bool active, uint32_t it) {
+  using Md = Model<DYN>;
+  using Rg = WsRing<DYN>;
+  constexpr int M = Md::M, Q = Md::Q;
+  Noise<DYN, JUMPS> nz;
+  draw_noise(nz, p, cs, (uint32_t)t, (uint32_t)k, it);
+  float u[M];
+#pragma unroll
+  for (int j = 0; j < M; ++j) u[j] = U[t * M + j];
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < M; ++j) slot[j * 64 + lane] = u[j] + nz.eps[j];
+#pragma unroll
+  for (int i = 0; i < Rg::NG; ++i) slot[(M + i) * 64 + lane] = nz.gust[i];
+  slot[(Rg::NF - 1) * 64 + lane] = state_free_cost<M, FORM>(p, cs, u, nz.eps);
+#pragma unroll
+  for (int j = 0; j < M; ++j) b.eps[(size_t)(t * M + j) * p.Ks + k] = nz.eps[j];
+  if constexpr (DEBUG) {
+    if (active) {
+      const size_t kt = (size_t)k * p.T + t;
+#pragma unroll
+      for (int j = 0; j < M; ++j) b.dbg_zD[kt * M + j] = nz.z[j];
+      b.dbg_N[kt] = nz.n;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) b.dbg_zJ[kt * Q + i] = JUMPS ? nz.z[M + i] : 0.f;
+    }
+  }
+}
+
+template <int DYN>
+struct WsState {
+  float x[Model<DYN>::N];
+  float S, comp;
+  bool crashed;
+};
+
+// One step of the state recursion from a ring slot: running cost on the
+// pre-step state, then the explicit Euler step (frozen once crashed).
+template <int DYN>
+__device__ __forceinline__ void ws_consume(const DevParams& p, const Consts& cs, WsState<DYN>& st,
+                                           const float* slot) {
+  using Md = Model<DYN>;
+  using Rg = WsRing<DYN>;
+  constexpr int N = Md::N, M = Md::M;
+  const int lane = threadIdx.x & 63;
+  float v[M], gust[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int j = 0; j < M; ++j) v[j] = slot[j * 64 + lane];
+#pragma unroll
+  for (int i = 0; i < Rg::NG; ++i) gust[i] = slot[(M + i) * 64 + lane];
+  const float pre = slot[(Rg::NF - 1) * 64 + lane];
+  float qx = 0.f;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    const float d = st.x[i] - cs.goal[i];
+    qx += cs.Q[i] * d * d;
+  }
+  if constexpr (Md::CAN_CRASH) qx += st.crashed ? p.pen : 0.f;
+  kahan_add(st.S, st.comp, qx * p.dt + pre);
+  if constexpr (Md::CAN_CRASH) {
+    float xn[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) xn[i] = st.x[i];
+    Md::step(xn, v, gust, p.dt, cs.mc);
+#pragma unroll
+    for (int i = 0; i < N; ++i) st.x[i] = st.crashed ? st.x[i] : xn[i];
+    st.crashed = st.crashed || Md::crashed(st.x, cs.mc);
+  } else {
+    Md::step(st.x, v, gust, p.dt, cs.mc);
+  }
+}
+
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED>
+__global__ __launch_bounds__(64 * WsWaves<DYN>::W) void rollout_ws_kernel(const DevParams p,
+                                                                         const Buffers b,
+                                                         const float* __restrict__ x0,
+                                                         const float* __restrict__ U, int R) {
+  using Md = Model<DYN>;
+  using Rg = WsRing<DYN>;
+  constexpr int N = Md::N;
+  constexpr int W = WsWaves<DYN>::W, NP = W - 1;  // waves, producer waves
+  constexpr int SLOT = Rg::NF * 64;  // floats per (step) slot
+  __shared__ float ring[2][kWsChunk][SLOT];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int k = blockIdx.x * kWsSamples + lane;
+  const bool active = k < p.K;
+  const uint32_t it = (uint32_t)b.stats->iteration;
+  const int T = p.T;
+  const int nch = (T + kWsChunk - 1) / kWsChunk;
+  __shared__ Consts cs;
+  stage_consts(cs, p);
+
+  WsState<DYN> st;
+#pragma unroll
+  for (int i = 0; i < N; ++i) st.x[i] = x0[i];
+  st.crashed = Md::CAN_CRASH ? Md::crashed(st.x, cs.mc) : false;
+  st.S = 0.f;
+  st.comp = 0.f;
+
+  for (int c = 0; c <= nch; ++c) {
+    if (wave > 0) {
+      if (c < nch) {
+        float(*buf)[SLOT] = ring[c & 1];
+        for (int s = wave - 1; s < kWsChunk; s += NP) {
+          const int t = c * kWsChunk + s;
+          if (t < T) ws_produce<DYN, JUMPS, DEBUG, FORM>(p, cs, b, U, buf[s], t, k, active, it);
+        }
+      }
+    } else if (c > 0) {
+      const int cc = c - 1;
+      float(*buf)[SLOT] = ring[cc & 1];
+      if ((cc + 1) * kWsChunk <= T) {
+#pragma unroll
+        for (int s = 0; s < kWsChunk; ++s) ws_consume<DYN>(p, cs, st, buf[s]);
+      } else {
+        for (int s = 0; s < T - cc * kWsChunk; ++s) ws_consume<DYN>(p, cs, st, buf[s]);
+      }
+    }
+    __syncthreads();
+  }
+
+  double Sd = 0.0;
+  if (wave == 0) {
+    float qf = 0.f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      const float d = st.x[i] - cs.goal[i];
+      qf += p.Qf[i] * d * d;
+    }
+    if constexpr (Md::CAN_CRASH) qf += st.crashed ? p.pen : 0.f;
+    kahan_add(st.S, st.comp, qf);
+    Sd = (double)st.S - (double)st.comp;
+    if (active) b.S[k] = Sd;
+  }
+  rollout_epilogue<kWsSamples, FUSED, 64 * W>(p, b, Sd, wave == 0 && active, R);
+}
+
+}  // namespace mppi

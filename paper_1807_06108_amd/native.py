@@ -52,7 +52,7 @@ class Config(ctypes.Structure):
         ("u_init", ctypes.c_float * 4), ("R", ctypes.c_float * 4),
         ("Q", ctypes.c_float * 12), ("Qf", ctypes.c_float * 12),
         ("x_goal", ctypes.c_float * 12), ("params", ctypes.c_float * 12),
-        ("crash_penalty", ctypes.c_float), ("reserved", ctypes.c_int32),
+        ("crash_penalty", ctypes.c_float), ("schedule", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("controller_id", ctypes.c_uint64),
         ("start_iteration", ctypes.c_uint64),
     ]

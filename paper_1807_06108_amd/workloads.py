@@ -44,7 +44,7 @@ def base_config(dynamics):
                 alpha=1.0, c=1.0, nu=0.0, count_law=0, cost_form=0,
                 debug_dump=0, sigma=[0.0] * 4, sigma_J=[0.0] * 4,
                 u_init=[0.0] * 4, R=[0.0] * 4, Q=[0.0] * 12, Qf=[0.0] * 12,
-                x_goal=[0.0] * 12, params=[0.0] * 12, crash_penalty=0.0,
+                x_goal=[0.0] * 12, params=[0.0] * 12, crash_penalty=0.0, schedule=0,
                 seed=DEFAULT_SEED, controller_id=0, start_iteration=0)
 
 

@@ -83,7 +83,7 @@ BAD = [
     ("dynamics", 3), ("K", 0), ("K", 2**24 + 1), ("T", 0), ("T", 4097), ("dt", 0.0),
     ("dt", float("nan")), ("lambda", 0.0), ("lambda", -1.0), ("c", 0.0), ("nu", -0.1),
     ("nu", float("inf")), ("alpha", float("nan")), ("count_law", 2), ("cost_form", 5),
-    ("debug_dump", 3), ("reserved", 1), ("sigma", [-1.0, 0, 0, 0]),
+    ("debug_dump", 3), ("schedule", 3), ("sigma", [-1.0, 0, 0, 0]),
     ("sigma_J", [float("nan"), 0, 0, 0]), ("controller_id", 2**24),
     ("start_iteration", 2**32), ("params", [0.0] * 12),
 ]
