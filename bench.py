@@ -1,21 +1,28 @@
 """Benchmark of the MPPI-on-jump-diffusion hot path on one MI355X.
 
-Default workload: closed-loop cartpole swing-up MPC, K=4096 samples, T=100
-steps, dt=0.02, 5 iterations per control step, receding-horizon shift and a
-simulated plant (jumps at 5/s with N(0, 10^2) amplitudes plus N(0, 1) noise)
-between control steps.  One bench "step" = one control step = 5 iterations
-(sampling, rollout, costs, weights, update) + shift + plant step, all on the
-device with the state and disturbances resident in HBM.  value =
-rollout-steps/s = K * T * iters * steps / wall time of the timed steps.
+Default workload (`cartpole_mpc`): closed-loop cartpole swing-up MPC, K=4096
+samples, T=100 steps, dt=0.02, 5 iterations per control step, receding-horizon
+shift, and a simulated plant (jumps at 5/s with N(0, 10^2) amplitudes plus
+N(0, 1) noise) between control steps.  One bench "step" = one control step =
+5 iterations (sampling, rollout, costs, weights, update) + shift + plant step,
+all on the device with state, control sequence and disturbances resident in
+HBM.  value = rollout-steps/s = K * T * iters * steps / wall time of the timed
+steps.
 
-Prints one JSON line with, besides the throughput, the per-control-step
-latency distribution (HIP events between steps), the dominant kernel's
-roofline (the fused rollout; VALU issue bound) and the CPU oracle baseline.
+The JSON line also carries
+  latency_ms       device time per control step (HIP events between steps),
+  host_loop_ms     state uploaded -> control step -> u0 downloaded, per control
+                   step (PCIe-inclusive; not the value),
+  roofline         the rollout kernel (dominant) against the VALU issue peak;
+                   its average duration comes from HIP events on its own
+                   stream, sampled on every PROFILE_EVERY-th control step of
+                   the timed region (events on every launch would perturb it),
+  cpu_baseline     the FP64 oracle on a bounded sample of the same loop.
 """
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -25,49 +32,81 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-# Algorithmic work of one sample-step of the fused rollout (the unit of the
-# throughput metric), counted from the method's operations, each weighted by
-# the VALU issue slots its gfx950 instruction occupies per lane (full rate = 1;
-# 32x32->64 multiply and transcendentals = 4, measured by an instruction-rate
-# probe).  Derivation per system in the design notes.
-ALG = {
-    # cartpole: Philox4x32-10 (20 mul64, 20 xor3-equivalents), Box-Muller
-    # (2 cvt, 2 mul, log, sqrt, sin, cos, 3 mul), count compare (6),
-    # perturbation (2), cost + IS + Kahan (24), dynamics + Euler (26 incl.
-    # sin, cos, rcp)
-    1: dict(fp32_flop=61, slots=20 * 4 + 20 + 4 + 4 * 4 + 5 + 6 + 2 + 24 + 23 + 3 * 4),
-    # quadrotor: 3 Philox blocks, 4 Box-Muller pairs, cost over 12 states,
-    # rigid-body dynamics with 6 sin/cos and 1 rcp
-    2: dict(fp32_flop=228, slots=3 * (20 * 4 + 20) + 4 * (4 * 4 + 7) + 9 + 70 + 110 + 7 * 4),
-}
-VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9    # CUs x SIMDs x lanes x clock
-FP32_PEAK_NONPACKED = 78.6e12             # v_fma_f32 on every lane
+# Algorithmic VALU work of one sample-step (the unit of the throughput
+# metric), counted from the method's operations, each weighted by the issue
+# slots of the gfx950 instruction that implements it (full rate 1; 32x32->64
+# multiply and transcendental 4, as measured by the instruction-rate probe).
+# Derivation in the design notes (rollout roofline section).
+ALG_SLOTS = {0: 187, 1: 219, 2: 653}
+ALG_FP32_FLOP = {0: 40, 1: 71, 2: 231}
+# 256 CUs x 128 full-rate lane-slots per CU-clock x 2.4 GHz (measured issue
+# rate of v_fma_f32; at 2 FLOP per slot this is the 157.3 TFLOP/s FP32 peak)
+VALU_PEAK_SLOTS = 256 * 128 * 2.4e9
+FP32_PEAK = 157.3e12
+PROFILE_EVERY = 8
+CSRC = os.path.join(ROOT, "paper_1807_06108_amd", "csrc")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rollout_traffic.json")
 
 
-def cpu_baseline(cfg, x0, U0, iters, budget_s=12.0):
-    """Oracle (FP64 NumPy) on a bounded sample of the same closed loop."""
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
-    from oracle import mppi as omppi
+def source_hash():
+    """Digest of the kernel sources (ties counter results to a kernel)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per rollout launch from the committed counter runs, if they
+    were taken on the current kernel sources (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != source_hash():
+        return None
+    w = rec.get("workloads", {}).get(workload)
+    return None if w is None else w["bytes_per_launch"]
+
+
+def cpu_baseline(cfg, x0, U0, iters, dist, budget_s):
+    """The oracle (FP64 NumPy, one thread) on a bounded sample of the same
+    closed loop: control steps with the same iteration indices and plant."""
     from oracle import models
-    from paper_1807_06108_amd import workloads
-    dist = workloads.plant_disturbance(10_000, cfg["dt"], 1.0, cfg["nu"], cfg["sigma_J"][0])
+    from oracle import mppi as omppi
     x = x0.astype(np.float64)
     U = U0.astype(np.float64)
     P = omppi.f32(cfg["params"])
+    dt = float(omppi.f32(cfg["dt"]))
     t0 = time.perf_counter()
     steps = 0
     while True:
         u0, U = omppi.control_step(cfg, x, U, steps * iters, iters)
         x = models.euler_step(cfg["dynamics"], x[None], (u0 + dist[steps])[None],
-                              np.zeros((1, 3)), float(omppi.f32(cfg["dt"])), P)[0]
+                              np.zeros((1, 3)), dt, P)[0]
         steps += 1
-        if time.perf_counter() - t0 > budget_s:
+        if time.perf_counter() - t0 > budget_s or steps >= len(dist):
             break
-    dt = time.perf_counter() - t0
-    return dict(value=cfg["K"] * cfg["T"] * iters * steps / dt, unit="rollout-steps/s",
+    el = time.perf_counter() - t0
+    return dict(value=cfg["K"] * cfg["T"] * iters * steps / el, unit="rollout-steps/s",
                 cores=1, kind="oracle",
-                sample="%d closed-loop control steps of the same workload (%d iterations each), "
-                       "%.1f s" % (steps, iters, dt))
+                sample="%d closed-loop control steps of this workload (%d iterations each, "
+                       "K=%d, T=%d), %.1f s, single thread" % (steps, iters, cfg["K"],
+                                                               cfg["T"], el))
+
+
+def calibrate_copy(nbytes=256 << 20, reps=4):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": nbytes, "launches": reps}), flush=True)
 
 
 def main():
@@ -78,15 +117,18 @@ def main():
     ap.add_argument("--workload", default="cartpole_mpc",
                     choices=["cartpole_mpc", "cartpole_single", "quadrotor_hover"])
     ap.add_argument("--iters", type=int, default=None)
+    ap.add_argument("--K", type=int, default=None, help="override the preset's sample count")
+    ap.add_argument("--T", type=int, default=None, help="override the preset's horizon")
     ap.add_argument("--schedule", default="auto", choices=["auto", "lane", "ws"],
                     help="rollout schedule (identical results)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--host-loop-steps", type=int, default=100)
+    ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the method's data-parallel axis (samples) "
-              "fits one MI355X and this build runs no multi-GPU path; use --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU: the method's parallel axis (samples) fits one "
+              "MI355X and no multi-GPU path is built; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -94,53 +136,80 @@ def main():
     from paper_1807_06108_amd.controller import Controller
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     cfg = workloads.PRESETS[args.workload]()
     cfg["schedule"] = {"auto": 0, "lane": 1, "ws": 2}[args.schedule]
+    if args.K:
+        cfg["K"] = args.K
+    if args.T:
+        cfg["T"] = args.T
     iters = args.iters or (5 if args.workload == "cartpole_mpc" else 1)
-    K, T = cfg["K"], cfg["T"]
-    n, m = len(workloads.x0_for(cfg)), workloads.DIMS[cfg["dynamics"]][1]
+    K, T, dyn = cfg["K"], cfg["T"], cfg["dynamics"]
+    n, m, q = workloads.DIMS[dyn]
     x0 = workloads.x0_for(cfg)
     U0 = workloads.U0_for(cfg)
-    total = args.steps + args.warmup
+    total = args.steps + args.warmup + args.host_loop_steps
     dist = np.zeros((total, m), dtype=np.float32)
-    if cfg["dynamics"] == 1:
-        dist[:, 0] = workloads.plant_disturbance(total, cfg["dt"], 1.0, cfg["nu"], cfg["sigma_J"][0])
+    if dyn == 1:
+        dist[:, 0] = workloads.plant_disturbance(total, cfg["dt"], 1.0, cfg["nu"],
+                                                 cfg["sigma_J"][0])
 
+    stream = torch.cuda.current_stream()
     ctl = Controller(cfg, U0)
     x = torch.tensor(x0, device="cuda")
     d = torch.tensor(dist, device="cuda")
     u0 = torch.empty(m, dtype=torch.float32, device="cuda")
-    stream = torch.cuda.current_stream()
 
     def control_step(i):
-        ctl.step(x, iters)
-        ctl.shift(out=u0)
+        ctl.control_step(x, iters, u0)
         ctl.plant_step(x, u0, d[i])
 
     for i in range(args.warmup):
         control_step(i)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    ctl.profile(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev[0].record(stream)
     for i in range(args.steps):
+        prof = i % PROFILE_EVERY == 0
+        if prof:
+            ctl.profile(True)
         control_step(args.warmup + i)
+        if prof:
+            ctl.profile(False)
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ctl.profile(False)
     roll_ms, launches = ctl.profile_read()
     lat = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
-    unit_steps = K * T * iters * args.steps
-    value = unit_steps / wall
+
+    # host in the loop: state uploaded, control step, u0 downloaded (timed);
+    # the plant then steps on the device and the state comes back (untimed)
+    host_lat = []
+    x_host = torch.empty(n, dtype=torch.float32, pin_memory=True)
+    u0_host = torch.empty(m, dtype=torch.float32, pin_memory=True)
+    x_host.copy_(x)
+    for i in range(args.host_loop_steps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        x.copy_(x_host, non_blocking=True)
+        ctl.control_step(x, iters, u0)
+        u0_host.copy_(u0, non_blocking=True)
+        torch.cuda.synchronize()
+        host_lat.append((time.perf_counter() - t1) * 1e3)
+        ctl.plant_step(x, u0, d[args.warmup + args.steps + i])
+        x_host.copy_(x)
+
+    value = K * T * iters * args.steps / wall
     avg_roll_s = roll_ms / launches * 1e-3
-    alg = ALG[cfg["dynamics"]]
-    achieved = alg["slots"] * K * T / avg_roll_s
-    flops = alg["fp32_flop"] * K * T / avg_roll_s
+    achieved = ALG_SLOTS[dyn] * K * T / avg_roll_s
+    flops = ALG_FP32_FLOP[dyn] * K * T / avg_roll_s
     line = {
-        "metric": "rollout-steps/sec (K*T*iters), plain per-controller launch",
+        "metric": "rollout-steps/sec (K*T*iters) + p99 MPC-step latency, plain "
+                  "per-controller launch",
         "value": value,
         "unit": "rollout-steps/s",
         "n_gpus": 1,
@@ -151,21 +220,31 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded Philox draws; seeded plant disturbances)",
+        "data": "synthetic (seeded Philox draws, seeded plant disturbances)",
         "config": {"workload": args.workload, "K": K, "T": T, "dt": cfg["dt"],
-                   "iters_per_control_step": iters, "dynamics": cfg["dynamics"],
-                   "nu": cfg["nu"], "form": "plain", "schedule": args.schedule},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "what": "device time per control step (iters + shift + plant)"},
-        "roofline": {"bound": "alu", "kernel": "rollout_kernel",
+                   "iters_per_control_step": iters, "dynamics": dyn, "nu": cfg["nu"],
+                   "form": "plain", "schedule": args.schedule},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)),
+                       "p99": float(np.percentile(lat, 99)),
+                       "what": "device time per control step (iterations + shift + plant)"},
+        "host_loop_ms": ({"p50": float(np.percentile(host_lat, 50)),
+                          "p99": float(np.percentile(host_lat, 99)), "steps": len(host_lat),
+                          "what": "state host->device, control step, u0 device->host, "
+                                  "synchronise"} if host_lat else None),
+        "roofline": {"bound": "alu",
+                     "kernel": "rollout (sampling, propagation, cost, weights, update)",
                      "achieved": achieved / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
                      "unit": "T VALU-slot/s", "frac": achieved / VALU_PEAK_SLOTS,
-                     "traffic": None, "avg_launch_us": avg_roll_s * 1e6,
-                     "fp32_tflops": flops / 1e12,
-                     "fp32_frac_nonpacked": flops / FP32_PEAK_NONPACKED},
+                     "traffic": (measured_traffic(args.workload)
+                                 if args.K is None and args.T is None else None),
+                     "avg_launch_us": avg_roll_s * 1e6, "launches_timed": launches,
+                     "slots_per_sample_step": ALG_SLOTS[dyn],
+                     "fp32_tflops": flops / 1e12, "fp32_frac": flops / FP32_PEAK},
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg, x0, U0, iters, args.cpu_budget)
+        line["cpu_baseline"] = cpu_baseline(cfg, x0, U0, iters,
+                                            dist[args.warmup:].astype(np.float64),
+                                            args.cpu_budget)
     print(json.dumps(line), flush=True)
 
 

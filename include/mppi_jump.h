@@ -173,6 +173,16 @@ int mppi_jump_init(const mppi_jump_config* cfg, void* d_workspace, size_t ws_byt
  * MPPI_ENONFINITE in the statistics (read with MPPI_ITEM_STATS). */
 int mppi_jump_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, void* stream);
 
+/* One MPC control step (Algorithm 1 loop body, Sec. V): `iters` >= 1
+ * iterations from d_x0 followed by the receding-horizon shift, with u_0 (the
+ * control to execute, [m] fp32) written to d_u0_out (device memory; may be
+ * NULL).  Equivalent to mppi_jump_step then mppi_jump_shift; when the
+ * update is applied inside the rollout kernel (at most 512 rollout
+ * workgroups) the shift and the u_0 output are folded into the last
+ * iteration's kernel. */
+int mppi_jump_control_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters,
+                           float* d_u0_out, void* stream);
+
 /* The two halves of one iteration, for callers that stage it:
  * rollout = sampling, propagation and path costs (fills S and eps, and the
  * min / normaliser statistics); update = weights and control update (reads

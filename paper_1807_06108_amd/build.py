@@ -36,5 +36,20 @@ def build(extra_flags=(), out=LIB, verbose=False):
     return out
 
 
+PROBE_SRC = os.path.join(HERE, "probe", "issue_rates.hip")
+PROBE_BIN = os.path.join(HERE, "probe", "issue_rates")
+
+
+def build_probe(verbose=False):
+    """Compile the VALU issue-rate probe (an executable for gfx950)."""
+    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", "-o", PROBE_BIN, PROBE_SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return PROBE_BIN
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_probe(verbose=True))

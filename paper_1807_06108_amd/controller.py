@@ -79,6 +79,16 @@ class Controller:
         native.check(native.lib().mppi_jump_step(self.ctx, _ptr(x), int(iters), self._s()))
         return x
 
+    def control_step(self, x0, iters=1, u0_out=None):
+        """Enqueue one MPC control step: `iters` iterations then the shift;
+        returns u_0 [m] (device tensor)."""
+        x = self._state(x0)
+        if u0_out is None:
+            u0_out = torch.empty(self.m, dtype=torch.float32, device=self.device)
+        native.check(native.lib().mppi_jump_control_step(self.ctx, _ptr(x), int(iters),
+                                                         _ptr(u0_out), self._s()))
+        return u0_out
+
     def rollout(self, x0):
         x = self._state(x0)
         native.check(native.lib().mppi_jump_rollout(self.ctx, _ptr(x), self._s()))

@@ -62,6 +62,17 @@ struct Buffers {
   float* dbg_zJ;      // [K][T][q]
 };
 
+// Receding-horizon shift folded into the last iteration of a control step:
+// u0_out[0..m) <- U[0] (device memory; may be null), U[t] <- U[t+1],
+// U[T-1] <- u_init (Algorithm 1), applied after the update by the last
+// workgroup of the fused epilogue.
+struct ShiftArgs {
+  float* u0_out;
+  int on;
+  int m;
+  float4 u_init;
+};
+
 // Per-sample-step constants of the rollout, staged in LDS at kernel start
 // (by the first 16 threads of any workgroup of at least 64 threads).
 // Read with wavefront-uniform addresses they land in vector registers, which
@@ -114,7 +125,7 @@ constexpr int kStageRows = 1024;  // partial rows staged in LDS per pass
 // this XCD, so one per workgroup instead of one per wavefront).
 template <int SPW, bool FUSED, int NT = kBlock>
 __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffers& b, double Sd,
-                                                 bool active, int R) {
+                                                 bool active, int R, const ShiftArgs sh = {}) {
   constexpr int NW = NT / 64;
   __shared__ double lds[NW];
   __shared__ double e_lds[SPW];
@@ -206,6 +217,26 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
         }
         for (; j < nwg; ++j) d0 += sc_lds[j] * wr[j];
         b.U[r] = (float)((double)b.U[r] + f * ((d0 + d1) + (d2 + d3)));
+      }
+    }
+    if (sh.on) {
+      __syncthreads();  // the updated rows are visible to the whole block
+      const int m = sh.m;
+      if (sh.u0_out != nullptr && threadIdx.x < m) sh.u0_out[threadIdx.x] = b.U[threadIdx.x];
+      for (int base = 0; base < R; base += NT) {
+        const int r = base + threadIdx.x;
+        float v = 0.f;
+        if (r < R) {
+          if (r + m < R) {
+            v = b.U[r + m];
+          } else {
+            const int j = r - (R - m);
+            v = j == 0 ? sh.u_init.x : j == 1 ? sh.u_init.y : j == 2 ? sh.u_init.z : sh.u_init.w;
+          }
+        }
+        __syncthreads();
+        if (r < R) b.U[r] = v;
+        __syncthreads();
       }
     }
   }
@@ -312,7 +343,8 @@ __device__ __forceinline__ float state_free_cost(const DevParams& p, const Const
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED>
 __global__ __launch_bounds__(256) void rollout_kernel(const DevParams p, const Buffers b,
                                                       const float* __restrict__ x0,
-                                                      const float* __restrict__ U, int R) {
+                                                      const float* __restrict__ U, int R,
+                                                      const ShiftArgs sh) {
   using Md = Model<DYN>;
   constexpr int N = Md::N, M = Md::M, Q = Md::Q;
   const int k = blockIdx.x * kBlock + threadIdx.x;
@@ -389,7 +421,7 @@ __global__ __launch_bounds__(256) void rollout_kernel(const DevParams p, const B
   kahan_add(S, comp, qf);
   const double Sd = (double)S - (double)comp;
   if (active) b.S[k] = Sd;
-  rollout_epilogue<kBlock, FUSED>(p, b, Sd, active, R);
+  rollout_epilogue<kBlock, FUSED>(p, b, Sd, active, R, sh);
 }
 
 // Statistics of caller-provided costs (mppi_jump_set of S), with the

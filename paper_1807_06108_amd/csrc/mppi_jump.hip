@@ -272,40 +272,43 @@ struct mppi_jump_ctx {
 namespace {
 
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED>
-int launch_rollout_t(mppi_jump_ctx* ctx, const float* x0, hipStream_t s) {
+int launch_rollout_t(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, const ShiftArgs& sh) {
   if (ctx->L.ws) {
     rollout_ws_kernel<DYN, JUMPS, DEBUG, FORM, FUSED><<<dim3(ctx->L.nwg), dim3(64 * WsWaves<DYN>::W),
-                                                       0, s>>>(ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R);
+                                                       0, s>>>(ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R, sh);
     LAUNCH_CHECK("rollout_ws_kernel");
   } else {
     rollout_kernel<DYN, JUMPS, DEBUG, FORM, FUSED>
-        <<<dim3(ctx->L.nwg), dim3(kBlock), 0, s>>>(ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R);
+        <<<dim3(ctx->L.nwg), dim3(kBlock), 0, s>>>(ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R, sh);
     LAUNCH_CHECK("rollout_kernel");
   }
   return MPPI_OK;
 }
 
 template <int DYN, bool JUMPS, bool DEBUG>
-int launch_rollout_form(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, bool fused) {
+int launch_rollout_form(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, bool fused,
+                        const ShiftArgs& sh) {
   const bool it = ctx->cfg.cost_form == MPPI_COST_IT;
   if (fused)
-    return it ? launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_IT, true>(ctx, x0, s)
-              : launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_SO, true>(ctx, x0, s);
-  return it ? launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_IT, false>(ctx, x0, s)
-            : launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_SO, false>(ctx, x0, s);
+    return it ? launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_IT, true>(ctx, x0, s, sh)
+              : launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_SO, true>(ctx, x0, s, sh);
+  return it ? launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_IT, false>(ctx, x0, s, sh)
+            : launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_SO, false>(ctx, x0, s, sh);
 }
 
 template <int DYN>
-int launch_rollout_dyn(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, bool fused) {
+int launch_rollout_dyn(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, bool fused,
+                       const ShiftArgs& sh) {
   const bool jumps = ctx->p.n_th > 0, dbg = ctx->cfg.debug_dump != 0;
   if (jumps)
-    return dbg ? launch_rollout_form<DYN, true, true>(ctx, x0, s, fused)
-               : launch_rollout_form<DYN, true, false>(ctx, x0, s, fused);
-  return dbg ? launch_rollout_form<DYN, false, true>(ctx, x0, s, fused)
-             : launch_rollout_form<DYN, false, false>(ctx, x0, s, fused);
+    return dbg ? launch_rollout_form<DYN, true, true>(ctx, x0, s, fused, sh)
+               : launch_rollout_form<DYN, true, false>(ctx, x0, s, fused, sh);
+  return dbg ? launch_rollout_form<DYN, false, true>(ctx, x0, s, fused, sh)
+             : launch_rollout_form<DYN, false, false>(ctx, x0, s, fused, sh);
 }
 
-int launch_rollout(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, bool fused) {
+int launch_rollout(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, bool fused,
+                   const ShiftArgs& sh = ShiftArgs{}) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (ctx->profiling) {
     if (ctx->events_used >= 4096) return fail(MPPI_EINVAL, "profiling buffer full (4096 launches)");
@@ -320,9 +323,9 @@ int launch_rollout(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, bool fuse
   }
   int rc;
   switch (ctx->cfg.dynamics) {
-    case MPPI_DYN_LINEAR: rc = launch_rollout_dyn<MPPI_DYN_LINEAR>(ctx, x0, s, fused); break;
-    case MPPI_DYN_CARTPOLE: rc = launch_rollout_dyn<MPPI_DYN_CARTPOLE>(ctx, x0, s, fused); break;
-    default: rc = launch_rollout_dyn<MPPI_DYN_QUADROTOR>(ctx, x0, s, fused); break;
+    case MPPI_DYN_LINEAR: rc = launch_rollout_dyn<MPPI_DYN_LINEAR>(ctx, x0, s, fused, sh); break;
+    case MPPI_DYN_CARTPOLE: rc = launch_rollout_dyn<MPPI_DYN_CARTPOLE>(ctx, x0, s, fused, sh); break;
+    default: rc = launch_rollout_dyn<MPPI_DYN_QUADROTOR>(ctx, x0, s, fused, sh); break;
   }
   if (rc != MPPI_OK) return rc;
   if (ctx->profiling) {
@@ -479,6 +482,35 @@ int mppi_jump_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, void* s
         rc = launch_update(ctx, s);
         if (rc != MPPI_OK) return rc;
       }
+      ctx->host_iteration += 1;
+    }
+    return ok();
+  });
+}
+
+int mppi_jump_control_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, float* d_u0_out,
+                           void* stream) {
+  return guarded([&]() -> int {
+    if (!ctx || !d_x0) return fail(MPPI_EINVAL, "NULL context or state");
+    if (iters < 1) return fail(MPPI_EINVAL, "iters=%d < 1", iters);
+    if (ctx->host_iteration + (uint64_t)iters > kTwo32)
+      return fail(MPPI_EINVAL, "iteration counter would pass 2^32");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!ctx->L.fused) {
+      int rc = mppi_jump_step(ctx, d_x0, iters, stream);
+      if (rc != MPPI_OK) return rc;
+      return mppi_jump_shift(ctx, d_u0_out, stream);
+    }
+    for (int i = 0; i < iters; ++i) {
+      ShiftArgs sh{};
+      if (i == iters - 1) {
+        sh.on = 1;
+        sh.u0_out = d_u0_out;
+        sh.m = ctx->m;
+        sh.u_init = u_init4(ctx->cfg);
+      }
+      const int rc = launch_rollout(ctx, d_x0, s, true, sh);
+      if (rc != MPPI_OK) return rc;
       ctx->host_iteration += 1;
     }
     return ok();

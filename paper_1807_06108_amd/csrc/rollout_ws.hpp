@@ -110,7 +110,8 @@ template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED>
 __global__ __launch_bounds__(64 * WsWaves<DYN>::W) void rollout_ws_kernel(const DevParams p,
                                                                          const Buffers b,
                                                          const float* __restrict__ x0,
-                                                         const float* __restrict__ U, int R) {
+                                                         const float* __restrict__ U, int R,
+                                                         const ShiftArgs sh) {
   using Md = Model<DYN>;
   using Rg = WsRing<DYN>;
   constexpr int N = Md::N;
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(64 * WsWaves<DYN>::W) void rollout_ws_kernel(const 
     Sd = (double)st.S - (double)st.comp;
     if (active) b.S[k] = Sd;
   }
-  rollout_epilogue<kWsSamples, FUSED, 64 * W>(p, b, Sd, wave == 0 && active, R);
+  rollout_epilogue<kWsSamples, FUSED, 64 * W>(p, b, Sd, wave == 0 && active, R, sh);
 }
 
 }  // namespace mppi

@@ -74,3 +74,30 @@ def test_large_K_uses_lane_schedule_and_staged_update():
     np.testing.assert_array_max_ulp(a[1], b[1], maxulp=1)
     W = a[3]
     assert abs(W.sum() - 1) < 1e-12
+
+
+@pytest.mark.parametrize("preset,K,T,iters", [
+    ("cartpole_mpc", 4096, 100, 5), ("quadrotor_hover", 1000, 37, 2),
+    ("cartpole_single", 300, 1500, 2), ("double_integrator", 64, 1, 1),
+    ("cartpole_single", 150_000, 8, 2),
+])
+def test_control_step_equals_step_then_shift(preset, K, T, iters):
+    """The fused control step (shift and u_0 folded into the last
+    iteration's kernel) gives exactly the sequence and u_0 of step + shift."""
+    cfg = workloads.PRESETS[preset](K=K, T=T)
+    U0 = workloads.U0_for(cfg, "random")
+    x0 = workloads.x0_for(cfg)
+    print("case", preset, K, T, iters, flush=True)
+    a = Controller(cfg, U0)
+    a.step(x0, iters)
+    u0_a = a.shift().cpu().numpy()
+    b = Controller(cfg, U0)
+    u0_b = b.control_step(x0, iters).cpu().numpy()
+    assert np.array_equal(u0_a, u0_b)
+    assert np.array_equal(a.U.cpu().numpy(), b.U.cpu().numpy())
+    assert a.stats() == b.stats()
+    # a second control step continues from the shifted sequence
+    a.step(x0, 1)
+    u1_a = a.shift().cpu().numpy()
+    u1_b = b.control_step(x0, 1).cpu().numpy()
+    assert np.array_equal(u1_a, u1_b)
