@@ -220,6 +220,43 @@ const char* mppi_jump_strerror(int code);
 /* Detail of the calling thread's last failure ("" if none). */
 const char* mppi_jump_last_error(void);
 
+/* ---- batched form: many controllers advanced by one launch ----
+ * A batch groups contexts created with the same rollout schedule (each with
+ * at most 512 rollout workgroups and without debug_dump) and advances all of
+ * them by one iteration per kernel launch: one grid over every controller's
+ * tiles, longest first, driven by a device table of their parameters and
+ * buffers.  Each controller keeps its own workspace, iteration counter and
+ * noise stream, so a batched iteration gives exactly the results of
+ * mppi_jump_step / mppi_jump_control_step on that controller alone.  The
+ * tables are built once at creation; step calls take no pointers and can be
+ * captured in a HIP graph and replayed. */
+typedef struct mppi_jump_batch mppi_jump_batch;
+
+/* Device scratch for a batch of n contexts (descriptor table, tile list,
+ * u_0 outputs [n][4] fp32), for a 256-byte aligned base.  Pure host function.
+ * EINVAL for NULL/mixed-schedule contexts; EUNSUPPORTED for a context whose
+ * update is not fused or that has debug_dump set. */
+int mppi_jump_batch_scratch_bytes(mppi_jump_ctx* const* ctxs, int32_t n, size_t* bytes);
+
+/* Build a batch over ctxs[0..n) with states d_x0[i] ([n_i] fp32 device
+ * pointers, read at every step); uploads the tables on `stream` and
+ * synchronises it.  The caller keeps the contexts and the scratch alive for
+ * the life of the batch. */
+int mppi_jump_batch_create(mppi_jump_ctx* const* ctxs, const float* const* d_x0, int32_t n,
+                           void* d_scratch, size_t scratch_bytes, void* stream,
+                           mppi_jump_batch** out);
+
+/* Enqueue `iters` iterations of every controller of the batch (one launch
+ * per iteration); with shift != 0 the last one also shifts every sequence
+ * and writes each controller's u_0 to its slot of the u_0 output array. */
+int mppi_jump_batch_step(mppi_jump_batch* batch, int32_t iters, int32_t shift, void* stream);
+
+/* Device address of the u_0 outputs, [n][4] fp32 (controller i at 4*i). */
+int mppi_jump_batch_u0(mppi_jump_batch* batch, float** d_u0);
+
+/* Free the host-side batch object. */
+int mppi_jump_batch_destroy(mppi_jump_batch* batch);
+
 /* ---- closed-loop and measurement helpers (not part of the method) ---- */
 
 /* Simulated plant for closed-loop runs: one explicit Euler step of the

@@ -169,6 +169,49 @@ class Controller:
         return ms.value, n.value
 
 
+class Batch:
+    """Many controllers advanced by one launch per iteration (batched form).
+
+    controllers: Controller objects created with the same schedule; states:
+    their state tensors ([n_i] fp32 on the device), read at every step."""
+
+    def __init__(self, controllers, states, stream=None):
+        self.controllers = list(controllers)
+        self.states = [torch.as_tensor(x, dtype=torch.float32, device="cuda").contiguous()
+                       for x in states]
+        n = len(self.controllers)
+        self.stream = stream
+        ctxs = (ctypes.c_void_p * n)(*[c.ctx.value for c in self.controllers])
+        xs = (ctypes.c_void_p * n)(*[x.data_ptr() for x in self.states])
+        nbytes = ctypes.c_size_t()
+        native.check(native.lib().mppi_jump_batch_scratch_bytes(ctxs, n, ctypes.byref(nbytes)))
+        self.scratch = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+        bt = ctypes.c_void_p()
+        native.check(native.lib().mppi_jump_batch_create(ctxs, xs, n, _ptr(self.scratch),
+                                                         nbytes.value, _stream_handle(stream),
+                                                         ctypes.byref(bt)))
+        self.bt = bt
+        u0 = ctypes.c_void_p()
+        native.check(native.lib().mppi_jump_batch_u0(bt, ctypes.byref(u0)))
+        off = u0.value - self.scratch.data_ptr()
+        self.u0 = self.scratch[off:off + 16 * n].view(torch.float32).view(n, 4)
+
+    def step(self, iters=1, shift=True):
+        native.check(native.lib().mppi_jump_batch_step(self.bt, int(iters), int(bool(shift)),
+                                                       _stream_handle(self.stream)))
+
+    def close(self):
+        if getattr(self, "bt", None):
+            native.lib().mppi_jump_batch_destroy(self.bt)
+            self.bt = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def philox(counters, key0, key1):
     """Device Philox4x32-10 blocks for uint32 counters [n, 4] (numpy)."""
     c = torch.as_tensor(np.ascontiguousarray(counters, dtype=np.uint32).view(np.int32),

@@ -123,9 +123,11 @@ constexpr int kStageRows = 1024;  // partial rows staged in LDS per pass
 // issues the workgroup's single device-scope release fence before the
 // arrival counter is incremented (a device-scope fence writes back the L2 of
 // this XCD, so one per workgroup instead of one per wavefront).
+// wg / nwg: this workgroup's index among the nwg workgroups of its controller.
 template <int SPW, bool FUSED, int NT = kBlock>
 __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffers& b, double Sd,
-                                                 bool active, int R, const ShiftArgs sh = {}) {
+                                                 bool active, int R, const ShiftArgs sh, int wg,
+                                                 int nwg) {
   constexpr int NW = NT / 64;
   __shared__ double lds[NW];
   __shared__ double e_lds[SPW];
@@ -136,8 +138,7 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
   const bool fin = active && isfinite(Sd);
   const double rho_wg = block_min<NW>(fin ? Sd : INFINITY, lds);
   const double e = fin ? exp(-(Sd - rho_wg) / p.lam_d) : 0.0;
-  const int k0 = blockIdx.x * SPW;
-  const int nwg = gridDim.x;
+  const int k0 = wg * SPW;
   if (active) b.E[k0 + threadIdx.x] = e;
   if (threadIdx.x < SPW) e_lds[threadIdx.x] = e;
   const double eta_wg = block_sum<NW>(e, lds);
@@ -164,20 +165,20 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
       }
       __syncthreads();
       if (wave == 0)
-        for (int i = lane; i < nrow; i += 64) b.wpart[(size_t)(base + i) * nwg + blockIdx.x] = stage[i];
+        for (int i = lane; i < nrow; i += 64) b.wpart[(size_t)(base + i) * nwg + wg] = stage[i];
       __syncthreads();
     }
   }
   if (wave == 0) {
     if (lane == 0) {
-      b.part[blockIdx.x].rho = rho_wg;
-      b.part[blockIdx.x].eta = eta_wg;
-      b.part[blockIdx.x].nfin = (int32_t)nfin;
+      b.part[wg].rho = rho_wg;
+      b.part[wg].eta = eta_wg;
+      b.part[wg].nfin = (int32_t)nfin;
     }
     __threadfence();
     if (lane == 0) {
       const uint32_t prev = atomicAdd(&b.counters[0], 1u);
-      is_last = (prev == gridDim.x - 1);
+      is_last = (prev == (uint32_t)nwg - 1);
     }
   }
   __syncthreads();
@@ -340,14 +341,15 @@ __device__ __forceinline__ float state_free_cost(const DevParams& p, const Const
 // FORM: MPPI_COST_IT or MPPI_COST_SO.  FUSED: the epilogue also applies the
 // update (one kernel per iteration); otherwise it only forms the statistics
 // and update_kernel follows.
+// One workgroup (tile wg of nwg) of the one-sample-per-lane rollout.
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED>
-__global__ __launch_bounds__(256) void rollout_kernel(const DevParams p, const Buffers b,
-                                                      const float* __restrict__ x0,
-                                                      const float* __restrict__ U, int R,
-                                                      const ShiftArgs sh) {
+__device__ __forceinline__ void rollout_lane_tile(const DevParams& p, const Buffers& b,
+                                                  const float* __restrict__ x0,
+                                                  const float* __restrict__ U, int R,
+                                                  const ShiftArgs& sh, int wg, int nwg) {
   using Md = Model<DYN>;
   constexpr int N = Md::N, M = Md::M, Q = Md::Q;
-  const int k = blockIdx.x * kBlock + threadIdx.x;
+  const int k = wg * kBlock + threadIdx.x;
   const bool active = k < p.K;
   const uint32_t it = (uint32_t)b.stats->iteration;
   __shared__ Consts cs;
@@ -421,7 +423,15 @@ __global__ __launch_bounds__(256) void rollout_kernel(const DevParams p, const B
   kahan_add(S, comp, qf);
   const double Sd = (double)S - (double)comp;
   if (active) b.S[k] = Sd;
-  rollout_epilogue<kBlock, FUSED>(p, b, Sd, active, R, sh);
+  rollout_epilogue<kBlock, FUSED>(p, b, Sd, active, R, sh, wg, nwg);
+}
+
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED>
+__global__ __launch_bounds__(256) void rollout_kernel(const DevParams p, const Buffers b,
+                                                      const float* __restrict__ x0,
+                                                      const float* __restrict__ U, int R,
+                                                      const ShiftArgs sh) {
+  rollout_lane_tile<DYN, JUMPS, DEBUG, FORM, FUSED>(p, b, x0, U, R, sh, blockIdx.x, gridDim.x);
 }
 
 // Statistics of caller-provided costs (mppi_jump_set of S), with the
@@ -431,7 +441,7 @@ __global__ __launch_bounds__(256) void restats_kernel(const DevParams p, const B
   const int k = blockIdx.x * SPW + threadIdx.x;
   const bool active = threadIdx.x < SPW && k < p.K;
   const double Sd = active ? b.S[k] : 0.0;
-  rollout_epilogue<SPW, false>(p, b, Sd, active, 0);
+  rollout_epilogue<SPW, false>(p, b, Sd, active, 0, ShiftArgs{}, blockIdx.x, gridDim.x);
 }
 
 // ------------------------------------------------------------------ update
@@ -561,3 +571,4 @@ __global__ void philox_kernel(const uint32_t* __restrict__ ctr, uint32_t k0, uin
 }  // namespace mppi
 
 #include "rollout_ws.hpp"
+#include "batch.hpp"

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 #include <utility>
@@ -275,7 +276,8 @@ template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED>
 int launch_rollout_t(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, const ShiftArgs& sh) {
   if (ctx->L.ws) {
     rollout_ws_kernel<DYN, JUMPS, DEBUG, FORM, FUSED><<<dim3(ctx->L.nwg), dim3(64 * WsWaves<DYN>::W),
-                                                       0, s>>>(ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R, sh);
+                                                       ws_ring_bytes<DYN>(), s>>>(
+        ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R, sh);
     LAUNCH_CHECK("rollout_ws_kernel");
   } else {
     rollout_kernel<DYN, JUMPS, DEBUG, FORM, FUSED>
@@ -598,6 +600,186 @@ int mppi_jump_set(mppi_jump_ctx* ctx, int32_t what, const void* src, size_t src_
     }
     return fail(MPPI_EINVAL, "item %d cannot be set", what);
   });
+}
+
+// ------------------------------------------------------------------ batch
+}  // extern "C"
+
+struct mppi_jump_batch {
+  std::vector<mppi_jump_ctx*> ctxs;
+  std::vector<BatchDesc> h_desc;
+  std::vector<BatchTile> h_tiles;
+  BatchDesc* d_desc = nullptr;
+  BatchTile* d_tiles = nullptr;
+  float* d_u0 = nullptr;
+  bool ws = false;
+  size_t dyn_lds = 0;
+};
+
+namespace {
+
+struct BatchLayout {
+  size_t desc, tiles, u0, total;
+  int ntiles;
+};
+
+int batch_check(mppi_jump_ctx* const* ctxs, int32_t n, BatchLayout& BL, bool& ws) {
+  if (!ctxs || n < 1) return fail(MPPI_EINVAL, "batch needs at least one context");
+  int ntiles = 0;
+  for (int i = 0; i < n; ++i) {
+    const mppi_jump_ctx* c = ctxs[i];
+    if (!c) return fail(MPPI_EINVAL, "context %d is NULL", i);
+    if (!c->L.fused)
+      return fail(MPPI_EUNSUPPORTED, "context %d: K=%d needs more than %d rollout workgroups", i,
+                  c->cfg.K, kFusedMaxWg);
+    if (c->cfg.debug_dump) return fail(MPPI_EUNSUPPORTED, "context %d has debug_dump set", i);
+    if (i == 0) ws = c->L.ws;
+    if (c->L.ws != ws) return fail(MPPI_EINVAL, "contexts of one batch must share a rollout schedule");
+    ntiles += c->L.nwg;
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes, 256);
+    return at;
+  };
+  BL.desc = take((size_t)n * sizeof(BatchDesc));
+  BL.tiles = take((size_t)ntiles * sizeof(BatchTile));
+  BL.u0 = take((size_t)n * 4 * sizeof(float));
+  BL.total = off;
+  BL.ntiles = ntiles;
+  return MPPI_OK;
+}
+
+// Tile cost estimate for the longest-first order: time steps times the
+// issue slots of one sample-step of the model.
+double tile_cost(const mppi_jump_ctx* c) {
+  const double per_step = c->cfg.dynamics == MPPI_DYN_QUADROTOR ? 653.0
+                          : c->cfg.dynamics == MPPI_DYN_CARTPOLE ? 219.0 : 187.0;
+  return per_step * c->cfg.T;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mppi_jump_batch_scratch_bytes(mppi_jump_ctx* const* ctxs, int32_t n, size_t* bytes) {
+  return guarded([&]() -> int {
+    if (!bytes) return fail(MPPI_EINVAL, "bytes is NULL");
+    BatchLayout BL;
+    bool ws;
+    const int rc = batch_check(ctxs, n, BL, ws);
+    if (rc != MPPI_OK) return rc;
+    *bytes = BL.total;
+    return ok();
+  });
+}
+
+int mppi_jump_batch_create(mppi_jump_ctx* const* ctxs, const float* const* d_x0, int32_t n,
+                           void* d_scratch, size_t scratch_bytes, void* stream,
+                           mppi_jump_batch** out) {
+  return guarded([&]() -> int {
+    if (!out) return fail(MPPI_EINVAL, "out is NULL");
+    *out = nullptr;
+    BatchLayout BL;
+    bool ws = false;
+    int rc = batch_check(ctxs, n, BL, ws);
+    if (rc != MPPI_OK) return rc;
+    if (!d_x0) return fail(MPPI_EINVAL, "state pointer array is NULL");
+    for (int i = 0; i < n; ++i)
+      if (!d_x0[i]) return fail(MPPI_EINVAL, "state pointer %d is NULL", i);
+    if (!d_scratch || ((uintptr_t)d_scratch & 255u))
+      return fail(MPPI_EWORKSPACE, "scratch must be a 256-byte aligned device pointer");
+    if (scratch_bytes < BL.total)
+      return fail(MPPI_EWORKSPACE, "scratch of %zu bytes < %zu needed", scratch_bytes, BL.total);
+    auto* bt = new mppi_jump_batch();
+    bt->ws = ws;
+    bt->ctxs.assign(ctxs, ctxs + n);
+    char* base = static_cast<char*>(d_scratch);
+    bt->d_desc = reinterpret_cast<BatchDesc*>(base + BL.desc);
+    bt->d_tiles = reinterpret_cast<BatchTile*>(base + BL.tiles);
+    bt->d_u0 = reinterpret_cast<float*>(base + BL.u0);
+    bt->h_desc.resize(n);
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) {
+      const mppi_jump_ctx* c = ctxs[i];
+      BatchDesc& d = bt->h_desc[i];
+      std::memset(&d, 0, sizeof d);
+      d.p = c->p;
+      d.b = c->b;
+      d.x0 = d_x0[i];
+      d.u0_out = bt->d_u0 + 4 * i;
+      d.u_init = u_init4(c->cfg);
+      d.R = c->L.R;
+      d.nwg = c->L.nwg;
+      d.dyn = c->cfg.dynamics;
+      d.jumps = c->p.n_th > 0 ? 1 : 0;
+      d.form = c->cfg.cost_form;
+      d.m = c->m;
+      order[i] = i;
+      if (ws) {
+        const size_t lds = c->cfg.dynamics == MPPI_DYN_QUADROTOR ? ws_ring_bytes<MPPI_DYN_QUADROTOR>()
+                           : c->cfg.dynamics == MPPI_DYN_CARTPOLE ? ws_ring_bytes<MPPI_DYN_CARTPOLE>()
+                                                                  : ws_ring_bytes<MPPI_DYN_LINEAR>();
+        if (lds > bt->dyn_lds) bt->dyn_lds = lds;
+      }
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return tile_cost(ctxs[a]) > tile_cost(ctxs[b]); });
+    bt->h_tiles.reserve(BL.ntiles);
+    for (int i : order)
+      for (int w = 0; w < ctxs[i]->L.nwg; ++w) bt->h_tiles.push_back(BatchTile{i, w});
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(bt->d_desc, bt->h_desc.data(), (size_t)n * sizeof(BatchDesc),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(bt->d_tiles, bt->h_tiles.data(), bt->h_tiles.size() * sizeof(BatchTile),
+                         hipMemcpyHostToDevice, s);
+    const std::vector<float> zeros((size_t)n * 4, 0.f);  // unused u_0 slots read as 0
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(bt->d_u0, zeros.data(), zeros.size() * sizeof(float),
+                         hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      delete bt;
+      return fail(MPPI_EDEVICE, "batch table upload: %s", hipGetErrorString(e));
+    }
+    *out = bt;
+    return ok();
+  });
+}
+
+int mppi_jump_batch_step(mppi_jump_batch* bt, int32_t iters, int32_t shift, void* stream) {
+  return guarded([&]() -> int {
+    if (!bt) return fail(MPPI_EINVAL, "NULL batch");
+    if (iters < 1) return fail(MPPI_EINVAL, "iters=%d < 1", iters);
+    for (auto* c : bt->ctxs)
+      if (c->host_iteration + (uint64_t)iters > kTwo32)
+        return fail(MPPI_EINVAL, "iteration counter would pass 2^32");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const dim3 grid((unsigned)bt->h_tiles.size()), block(kBlock);
+    for (int i = 0; i < iters; ++i) {
+      const int sh = (shift && i == iters - 1) ? 1 : 0;
+      if (bt->ws)
+        batch_rollout_kernel<true><<<grid, block, bt->dyn_lds, s>>>(bt->d_desc, bt->d_tiles, sh);
+      else
+        batch_rollout_kernel<false><<<grid, block, 0, s>>>(bt->d_desc, bt->d_tiles, sh);
+      LAUNCH_CHECK("batch_rollout_kernel");
+    }
+    for (auto* c : bt->ctxs) c->host_iteration += (uint64_t)iters;
+    return ok();
+  });
+}
+
+int mppi_jump_batch_u0(mppi_jump_batch* bt, float** d_u0) {
+  if (!bt || !d_u0) return fail(MPPI_EINVAL, "NULL argument");
+  *d_u0 = bt->d_u0;
+  return ok();
+}
+
+int mppi_jump_batch_destroy(mppi_jump_batch* bt) {
+  delete bt;
+  return ok();
 }
 
 int mppi_jump_destroy(mppi_jump_ctx* ctx) {

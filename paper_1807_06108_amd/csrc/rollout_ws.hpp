@@ -31,6 +31,11 @@ struct WsRing {
   static constexpr int NF = Md::M + NG + 1;               // v[M], gust[NG], state-free cost
 };
 
+template <int DYN>
+constexpr size_t ws_ring_bytes() {
+  return sizeof(float) * 2 * kWsChunk * WsRing<DYN>::NF * 64;
+}
+
 template <int DYN, bool JUMPS, bool DEBUG, int FORM>
 __device__ __forceinline__ void ws_produce(const DevParams& p, const Consts& cs, const Buffers& b,
                                            const float* __restrict__ U, float* slot, int t,
@@ -106,20 +111,23 @@ __device__ __forceinline__ void ws_consume(const DevParams& p, const Consts& cs,
   }
 }
 
-template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED>
-__global__ __launch_bounds__(64 * WsWaves<DYN>::W) void rollout_ws_kernel(const DevParams p,
-                                                                         const Buffers b,
-                                                         const float* __restrict__ x0,
-                                                         const float* __restrict__ U, int R,
-                                                         const ShiftArgs sh) {
+// One workgroup (tile wg of nwg) of the wave-specialised rollout, W waves.
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, int W>
+__device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffers& b,
+                                                const float* __restrict__ x0,
+                                                const float* __restrict__ U, int R,
+                                                const ShiftArgs& sh, int wg, int nwg) {
   using Md = Model<DYN>;
   using Rg = WsRing<DYN>;
   constexpr int N = Md::N;
-  constexpr int W = WsWaves<DYN>::W, NP = W - 1;  // waves, producer waves
+  constexpr int NP = W - 1;  // producer waves
   constexpr int SLOT = Rg::NF * 64;  // floats per (step) slot
-  __shared__ float ring[2][kWsChunk][SLOT];
+  // the ring lives in dynamic LDS (ws_ring_bytes<DYN>() at launch), so that
+  // kernels containing several model variants share one allocation
+  extern __shared__ float ws_dyn_lds[];
+  float(*ring)[kWsChunk][SLOT] = reinterpret_cast<float(*)[kWsChunk][SLOT]>(ws_dyn_lds);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int k = blockIdx.x * kWsSamples + lane;
+  const int k = wg * kWsSamples + lane;
   const bool active = k < p.K;
   const uint32_t it = (uint32_t)b.stats->iteration;
   const int T = p.T;
@@ -169,7 +177,17 @@ __global__ __launch_bounds__(64 * WsWaves<DYN>::W) void rollout_ws_kernel(const 
     Sd = (double)st.S - (double)st.comp;
     if (active) b.S[k] = Sd;
   }
-  rollout_epilogue<kWsSamples, FUSED, 64 * W>(p, b, Sd, wave == 0 && active, R, sh);
+  rollout_epilogue<kWsSamples, FUSED, 64 * W>(p, b, Sd, wave == 0 && active, R, sh, wg, nwg);
+}
+
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED>
+__global__ __launch_bounds__(64 * WsWaves<DYN>::W) void rollout_ws_kernel(const DevParams p,
+                                                                         const Buffers b,
+                                                                         const float* __restrict__ x0,
+                                                                         const float* __restrict__ U,
+                                                                         int R, const ShiftArgs sh) {
+  rollout_ws_tile<DYN, JUMPS, DEBUG, FORM, FUSED, WsWaves<DYN>::W>(p, b, x0, U, R, sh, blockIdx.x,
+                                                                   gridDim.x);
 }
 
 }  // namespace mppi

@@ -115,6 +115,16 @@ _PROTOS = {
     "mppi_jump_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "mppi_jump_last_error": (ctypes.c_char_p, []),
     "mppi_jump_plant_step": (ctypes.c_int, [ctypes.c_void_p] * 5),
+    "mppi_jump_batch_scratch_bytes": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                                     ctypes.POINTER(ctypes.c_size_t)]),
+    "mppi_jump_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p),
+                                              ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                              ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                              ctypes.POINTER(ctypes.c_void_p)]),
+    "mppi_jump_batch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_void_p]),
+    "mppi_jump_batch_u0": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "mppi_jump_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "mppi_jump_philox": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                         ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "mppi_jump_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
