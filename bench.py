@@ -97,6 +97,60 @@ def cpu_baseline(cfg, x0, U0, iters, dist, budget_s):
                                                                cfg["T"], el))
 
 
+def batched_measure(n_ctl, ticks, warmup, seed=42):
+    """Batched form against plain per-controller launches on the same
+    controller set (half cartpole, half quadrotor, K in {512..8192}, T in
+    [30, 150], nu in [0, 10]/s): one tick = one iteration + shift of every
+    controller from its own state.  The batched tick is one graph replay
+    (one launch); the plain tick is n_ctl control-step launches in sequence."""
+    import torch
+    from paper_1807_06108_amd import autotune, workloads
+    from paper_1807_06108_amd.controller import Controller
+    cset = workloads.random_controllers(n_ctl, seed=seed)
+    cfgs = [c for c, _ in cset]
+    states = [torch.tensor(x, device="cuda") for _, x in cset]
+    work = sum(c["K"] * c["T"] for c in cfgs)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, n):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        for i in range(n):
+            fn()
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(n)])
+        return dict(value=work * n / wall, unit="rollout-steps/s", ms_per_tick=wall / n * 1e3,
+                    p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)))
+
+    ctls, batch, report = autotune.build_batch(cfgs, states)
+    for _ in range(warmup):
+        batch.step(iters=1, shift=True)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        batch.step(iters=1, shift=True)
+    torch.cuda.synchronize()
+    batched = timed(g.replay, ticks)
+    sched = report["schedule"]
+    plain_ctls = [Controller(dict(c, schedule=0)) for c in cfgs]
+    u0 = torch.empty(4, device="cuda")
+
+    def plain_tick():
+        for c, x in zip(plain_ctls, states):
+            c.control_step(x, 1, u0)
+    for _ in range(warmup):
+        plain_tick()
+    plain = timed(plain_tick, ticks)
+    return {"controllers": n_ctl, "rollout_steps_per_tick": work,
+            "schedule": {1: "lane", 2: "ws"}[sched], "autotune_ms": report["timings_ms"],
+            "batched_graph": batched, "plain_sequential": plain,
+            "speedup": batched["value"] / plain["value"]}
+
+
 def calibrate_copy(nbytes=256 << 20, reps=4):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -125,6 +179,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--host-loop-steps", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--batched-controllers", type=int, default=256)
+    ap.add_argument("--batched-ticks", type=int, default=20,
+                    help="0 skips the batched-form comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the method's parallel axis (samples) fits one "
@@ -241,6 +298,8 @@ def main():
                      "slots_per_sample_step": ALG_SLOTS[dyn],
                      "fp32_tflops": flops / 1e12, "fp32_frac": flops / FP32_PEAK},
     }
+    if args.batched_ticks > 0:
+        line["batched"] = batched_measure(args.batched_controllers, args.batched_ticks, 3)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg, x0, U0, iters,
                                             dist[args.warmup:].astype(np.float64),
