@@ -257,6 +257,70 @@ int mppi_jump_batch_u0(mppi_jump_batch* batch, float** d_u0);
 /* Free the host-side batch object. */
 int mppi_jump_batch_destroy(mppi_jump_batch* batch);
 
+/* ---- serving form: ticks over a resident pool ----
+ *
+ * A pool holds n contexts resident (each with its own workspace, U,
+ * iteration counter and noise stream; the same conditions as a batch) and
+ * advances any subset of them per tick: one MPC step per request (iters
+ * iterations of Algorithm 1 from the request's state, then the shift), all
+ * requests of a tick in one grid per iteration, longest first.  A request's
+ * result depends only on its controller's own sequence of requests, never on
+ * which other requests share its tick.
+ *
+ * A tick is staged through one of max_inflight slots: the host writes the
+ * request record to the slot's part of the caller's pinned staging, the tick
+ * uploads it, runs, and copies u_0 (and the plant's next state) back to the
+ * staging; results are taken with mppi_jump_pool_results once the tick has
+ * finished.  Ticks on different slots may be in flight together on different
+ * streams; a controller may belong to one tick in flight at a time and a
+ * slot holds one tick until its results are taken (both are checked: EINVAL).
+ * Calls on one pool are not thread-safe.  While a context belongs to a pool,
+ * the caller must not run it through other entry points concurrently. */
+typedef struct mppi_jump_pool mppi_jump_pool;
+
+#define MPPI_JUMP_POOL_MAX_INFLIGHT 16
+
+/* Sizes for a pool over ctxs[0..n) with max_inflight slots: device scratch
+ * (descriptor table and per-slot request records) and pinned host staging,
+ * both for 256-byte aligned bases.  Pure host function.  Same context
+ * conditions as mppi_jump_batch_scratch_bytes; EINVAL for max_inflight out
+ * of [1, MPPI_JUMP_POOL_MAX_INFLIGHT]. */
+int mppi_jump_pool_bytes(mppi_jump_ctx* const* ctxs, int32_t n, int32_t max_inflight,
+                         size_t* device_bytes, size_t* pinned_host_bytes);
+
+/* Build a pool: uploads the descriptor table on `stream`, synchronises it,
+ * and zeroes the staging.  d_scratch is device memory, h_pinned is
+ * page-locked host memory (e.g. hipHostMalloc); the caller owns both and the
+ * contexts and keeps them alive for the life of the pool. */
+int mppi_jump_pool_create(mppi_jump_ctx* const* ctxs, int32_t n, int32_t max_inflight,
+                          void* d_scratch, size_t device_bytes, void* h_pinned,
+                          size_t pinned_bytes, void* stream, mppi_jump_pool** out);
+
+/* Enqueue a tick on `stream` through `slot`: for each request i < count,
+ * controller ids[i] (distinct, in [0, n)) takes iters iterations from the
+ * host state states[12 i .. 12 i + n_i) (fp32) and shifts.  With dist
+ * (host, [count][4] fp32, disturbance added to the control channels) the
+ * tick then steps each request's simulated plant once from its state under
+ * u_0 + dist.  Host arrays are read during the call only.  Asynchronous. */
+int mppi_jump_pool_tick(mppi_jump_pool* pool, const int32_t* ids, const float* states,
+                        const float* dist, int32_t count, int32_t iters, int32_t slot,
+                        void* stream);
+
+/* *finished = 1 when the slot holds no tick or its tick has finished on the
+ * device, else 0.  Does not block. */
+int mppi_jump_pool_query(mppi_jump_pool* pool, int32_t slot, int32_t* finished);
+
+/* Take the results of the slot's finished tick, in the order of its
+ * requests: ids [count], u_0 [count][4] fp32 (unused channels 0) and, if the
+ * tick stepped the plant, the next plant states [count][12] fp32 (each
+ * output may be NULL).  Frees the slot and its controllers for new ticks.
+ * EINVAL if the slot holds no tick or the tick has not finished. */
+int mppi_jump_pool_results(mppi_jump_pool* pool, int32_t slot, int32_t* ids, float* u0,
+                           float* x_next, int32_t* count);
+
+/* Free the host-side pool object (its events included). */
+int mppi_jump_pool_destroy(mppi_jump_pool* pool);
+
 /* ---- closed-loop and measurement helpers (not part of the method) ---- */
 
 /* Simulated plant for closed-loop runs: one explicit Euler step of the

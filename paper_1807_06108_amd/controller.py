@@ -212,6 +212,80 @@ class Batch:
             pass
 
 
+def _np_ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+class Pool:
+    """Resident controllers served by ticks over any subset (serving form).
+
+    controllers: Controller objects created with the same schedule.
+    max_inflight: number of slots, i.e. ticks that may be in flight at once
+    (each on the stream given to tick()).  Host staging is page-locked memory
+    owned by this object."""
+
+    def __init__(self, controllers, max_inflight=4, stream=None):
+        self.controllers = list(controllers)
+        n = self.n = len(self.controllers)
+        self.max_inflight = int(max_inflight)
+        ctxs = (ctypes.c_void_p * n)(*[c.ctx.value for c in self.controllers])
+        dbytes, hbytes = ctypes.c_size_t(), ctypes.c_size_t()
+        native.check(native.lib().mppi_jump_pool_bytes(ctxs, n, self.max_inflight,
+                                                       ctypes.byref(dbytes), ctypes.byref(hbytes)))
+        self.device_bytes, self.host_bytes = dbytes.value, hbytes.value
+        self.scratch = torch.empty(dbytes.value, dtype=torch.uint8, device="cuda")
+        self._pinned = torch.empty(hbytes.value + 256, dtype=torch.uint8, pin_memory=True)
+        off = (-self._pinned.data_ptr()) % 256
+        pl = ctypes.c_void_p()
+        native.check(native.lib().mppi_jump_pool_create(
+            ctxs, n, self.max_inflight, _ptr(self.scratch), dbytes.value,
+            ctypes.c_void_p(self._pinned.data_ptr() + off), hbytes.value,
+            _stream_handle(stream), ctypes.byref(pl)))
+        self.pl = pl
+        self._count = [0] * self.max_inflight
+
+    def tick(self, ids, states, dist=None, iters=1, slot=0, stream=None):
+        """Enqueue one MPC step for controllers ids (int array [c]) from host
+        states [c, 12] (fp32); with dist [c, 4] also step each plant."""
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        states = np.ascontiguousarray(states, dtype=np.float32).reshape(len(ids), 12)
+        if dist is not None:
+            dist = np.ascontiguousarray(dist, dtype=np.float32).reshape(len(ids), 4)
+        native.check(native.lib().mppi_jump_pool_tick(self.pl, _np_ptr(ids), _np_ptr(states),
+                                                      _np_ptr(dist), len(ids), int(iters),
+                                                      int(slot), _stream_handle(stream)))
+        self._count[slot] = len(ids)
+
+    def finished(self, slot):
+        f = ctypes.c_int32()
+        native.check(native.lib().mppi_jump_pool_query(self.pl, int(slot), ctypes.byref(f)))
+        return bool(f.value)
+
+    def results(self, slot, plant=True):
+        """(ids [c], u0 [c, 4], x_next [c, 12] or None) of the slot's finished
+        tick, in request order."""
+        c = self._count[slot]
+        ids = np.empty(c, dtype=np.int32)
+        u0 = np.empty((c, 4), dtype=np.float32)
+        xn = np.empty((c, 12), dtype=np.float32) if plant else None
+        cnt = ctypes.c_int32()
+        native.check(native.lib().mppi_jump_pool_results(self.pl, int(slot), _np_ptr(ids),
+                                                         _np_ptr(u0), _np_ptr(xn),
+                                                         ctypes.byref(cnt)))
+        return ids, u0, xn
+
+    def close(self):
+        if getattr(self, "pl", None):
+            native.lib().mppi_jump_pool_destroy(self.pl)
+            self.pl = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def philox(counters, key0, key1):
     """Device Philox4x32-10 blocks for uint32 counters [n, 4] (numpy)."""
     c = torch.as_tensor(np.ascontiguousarray(counters, dtype=np.uint32).view(np.int32),

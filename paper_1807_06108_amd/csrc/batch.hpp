@@ -70,3 +70,84 @@ __global__ __launch_bounds__(256) void batch_rollout_kernel(const BatchDesc* __r
 }
 
 }  // namespace mppi
+
+namespace mppi {
+
+// Serving form: a tick advances a subset of a resident pool.  The request
+// record of a tick (device memory) holds, in longest-first order, the
+// controller ids [count], the tile prefix [count + 1], the states
+// [count][12] and the plant disturbances [count][4]; workgroup b finds its
+// request by binary search over the prefix.  Request i writes u_0 to
+// out[16 i .. 16 i + m) and, when the plant runs, the next plant state to
+// out[16 i + 4 .. 16 i + 4 + n).
+struct PoolTick {
+  const int* ids;
+  const int* prefix;
+  const float* states;
+  const float* dist;
+  float* out;
+  int count;
+  int shift;
+};
+
+constexpr int kPoolOut = 16;
+
+__device__ __forceinline__ int find_request(const int* prefix, int count, int b) {
+  int lo = 0, hi = count;  // prefix[lo] <= b < prefix[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= b)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <bool WS>
+__global__ __launch_bounds__(256) void pool_rollout_kernel(const BatchDesc* __restrict__ descs,
+                                                           const PoolTick tick) {
+  const int i = find_request(tick.prefix, tick.count, blockIdx.x);
+  BatchDesc d = descs[tick.ids[i]];
+  d.x0 = tick.states + 12 * i;
+  ShiftArgs sh;
+  sh.on = tick.shift;
+  sh.u0_out = tick.out + kPoolOut * i;
+  sh.m = d.m;
+  sh.u_init = d.u_init;
+  batch_tile<WS>(d, sh, blockIdx.x - tick.prefix[i]);
+}
+
+template <int DYN>
+__device__ __forceinline__ void pool_plant_one(const DevParams& p, const float* x, const float* d,
+                                               float* out) {
+  using Md = Model<DYN>;
+  float s[Md::N], v[Md::M];
+  const float gust[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int j = 0; j < Md::N; ++j) s[j] = x[j];
+#pragma unroll
+  for (int j = 0; j < Md::M; ++j) v[j] = out[j] + d[j];
+  Md::step(s, v, gust, p.dt, p.mc);
+#pragma unroll
+  for (int j = 0; j < Md::N; ++j) out[4 + j] = s[j];
+}
+
+// Simulated plant of each request: one explicit Euler step from the request
+// state under u_0 + disturbance (the same step as plant_kernel).
+__global__ __launch_bounds__(64) void pool_plant_kernel(const BatchDesc* __restrict__ descs,
+                                                        const PoolTick tick) {
+  const int i = blockIdx.x * 64 + threadIdx.x;
+  if (i >= tick.count) return;
+  const BatchDesc& d = descs[tick.ids[i]];
+  const float* x = tick.states + 12 * i;
+  const float* w = tick.dist + 4 * i;
+  float* out = tick.out + kPoolOut * i;
+  switch (d.dyn) {
+    case MPPI_DYN_LINEAR: pool_plant_one<MPPI_DYN_LINEAR>(d.p, x, w, out); break;
+    case MPPI_DYN_CARTPOLE: pool_plant_one<MPPI_DYN_CARTPOLE>(d.p, x, w, out); break;
+    default: pool_plant_one<MPPI_DYN_QUADROTOR>(d.p, x, w, out); break;
+  }
+}
+
+}  // namespace mppi

@@ -11,6 +11,7 @@
 #include <new>
 #include <string>
 #include <utility>
+#include <memory>
 #include <vector>
 
 #include "../../include/mppi_jump.h"
@@ -779,6 +780,293 @@ int mppi_jump_batch_u0(mppi_jump_batch* bt, float** d_u0) {
 
 int mppi_jump_batch_destroy(mppi_jump_batch* bt) {
   delete bt;
+  return ok();
+}
+
+// ------------------------------------------------------------------ pool
+}  // extern "C"
+
+namespace {
+
+// Request record of one slot: ids [n], prefix [n + 1], states [n][12],
+// disturbances [n][4], outputs [n][16] (4-byte words; parts 256-byte aligned).
+struct SlotLayout {
+  size_t ids, prefix, states, dist, out, total;
+};
+
+SlotLayout slot_layout(int n) {
+  SlotLayout S{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes, 256);
+    return at;
+  };
+  S.ids = take((size_t)n * 4);
+  S.prefix = take((size_t)(n + 1) * 4);
+  S.states = take((size_t)n * 12 * 4);
+  S.dist = take((size_t)n * 4 * 4);
+  S.out = take((size_t)n * kPoolOut * 4);
+  S.total = off;
+  return S;
+}
+
+struct PoolSlot {
+  hipEvent_t done = nullptr;
+  bool pending = false;       // a tick was enqueued and its results not yet taken
+  bool plant = false;         // that tick stepped the plant
+  std::vector<int> order;     // record position j holds the caller's request order[j]
+  std::vector<int> ids;       // the caller's ids, in the caller's order
+  int count = 0;
+};
+
+}  // namespace
+
+struct mppi_jump_pool {
+  std::vector<mppi_jump_ctx*> ctxs;
+  std::vector<double> cost;
+  std::vector<int> busy;      // slot whose tick holds the controller, or -1
+  std::vector<PoolSlot> slots;
+  BatchDesc* d_desc = nullptr;
+  char* d_slots = nullptr;
+  char* h_slots = nullptr;
+  SlotLayout S{};
+  int n = 0;
+  bool ws = false;
+  size_t dyn_lds = 0;
+  ~mppi_jump_pool() {
+    for (auto& sl : slots)
+      if (sl.done) (void)hipEventDestroy(sl.done);
+  }
+};
+
+extern "C" {
+
+int mppi_jump_pool_bytes(mppi_jump_ctx* const* ctxs, int32_t n, int32_t max_inflight,
+                         size_t* device_bytes, size_t* pinned_host_bytes) {
+  return guarded([&]() -> int {
+    if (!device_bytes || !pinned_host_bytes) return fail(MPPI_EINVAL, "NULL output");
+    if (max_inflight < 1 || max_inflight > MPPI_JUMP_POOL_MAX_INFLIGHT)
+      return fail(MPPI_EINVAL, "max_inflight=%d out of [1, %d]", max_inflight,
+                  MPPI_JUMP_POOL_MAX_INFLIGHT);
+    BatchLayout BL;
+    bool ws;
+    const int rc = batch_check(ctxs, n, BL, ws);
+    if (rc != MPPI_OK) return rc;
+    const SlotLayout S = slot_layout(n);
+    *device_bytes = align_up((size_t)n * sizeof(BatchDesc), 256) + S.total * max_inflight;
+    *pinned_host_bytes = S.total * max_inflight;
+    return ok();
+  });
+}
+
+int mppi_jump_pool_create(mppi_jump_ctx* const* ctxs, int32_t n, int32_t max_inflight,
+                          void* d_scratch, size_t device_bytes, void* h_pinned,
+                          size_t pinned_bytes, void* stream, mppi_jump_pool** out) {
+  return guarded([&]() -> int {
+    if (!out) return fail(MPPI_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t need_d = 0, need_h = 0;
+    const int rc = mppi_jump_pool_bytes(ctxs, n, max_inflight, &need_d, &need_h);
+    if (rc != MPPI_OK) return rc;
+    if (!d_scratch || ((uintptr_t)d_scratch & 255u) || device_bytes < need_d)
+      return fail(MPPI_EWORKSPACE, "device scratch missing, misaligned or below %zu bytes", need_d);
+    if (!h_pinned || ((uintptr_t)h_pinned & 255u) || pinned_bytes < need_h)
+      return fail(MPPI_EWORKSPACE, "pinned staging missing, misaligned or below %zu bytes", need_h);
+    std::unique_ptr<mppi_jump_pool> pl(new mppi_jump_pool());
+    pl->ctxs.assign(ctxs, ctxs + n);
+    pl->n = n;
+    pl->ws = ctxs[0]->L.ws;
+    pl->S = slot_layout(n);
+    pl->busy.assign(n, -1);
+    pl->slots.resize(max_inflight);
+    for (auto& sl : pl->slots) HIP_TRY(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    char* base = static_cast<char*>(d_scratch);
+    pl->d_desc = reinterpret_cast<BatchDesc*>(base);
+    pl->d_slots = base + align_up((size_t)n * sizeof(BatchDesc), 256);
+    pl->h_slots = static_cast<char*>(h_pinned);
+    std::vector<BatchDesc> h_desc(n);
+    pl->cost.resize(n);
+    for (int i = 0; i < n; ++i) {
+      const mppi_jump_ctx* c = ctxs[i];
+      BatchDesc& d = h_desc[i];
+      std::memset(&d, 0, sizeof d);
+      d.p = c->p;
+      d.b = c->b;
+      d.u_init = u_init4(c->cfg);
+      d.R = c->L.R;
+      d.nwg = c->L.nwg;
+      d.dyn = c->cfg.dynamics;
+      d.jumps = c->p.n_th > 0 ? 1 : 0;
+      d.form = c->cfg.cost_form;
+      d.m = c->m;
+      pl->cost[i] = tile_cost(c);
+      if (pl->ws) {
+        const size_t lds = c->cfg.dynamics == MPPI_DYN_QUADROTOR ? ws_ring_bytes<MPPI_DYN_QUADROTOR>()
+                           : c->cfg.dynamics == MPPI_DYN_CARTPOLE ? ws_ring_bytes<MPPI_DYN_CARTPOLE>()
+                                                                  : ws_ring_bytes<MPPI_DYN_LINEAR>();
+        if (lds > pl->dyn_lds) pl->dyn_lds = lds;
+      }
+    }
+    // the staging is zeroed once so that unused state / disturbance words
+    // of a request are defined
+    std::memset(pl->h_slots, 0, need_h);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(pl->d_desc, h_desc.data(), (size_t)n * sizeof(BatchDesc),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *out = pl.release();
+    return ok();
+  });
+}
+
+namespace {
+
+// Whether the tick last enqueued on a slot has finished on the device.
+int slot_finished(mppi_jump_pool* pl, int slot, bool* finished) {
+  PoolSlot& sl = pl->slots[slot];
+  if (!sl.pending) {
+    *finished = true;
+    return MPPI_OK;
+  }
+  const hipError_t e = hipEventQuery(sl.done);
+  if (e == hipErrorNotReady) {
+    *finished = false;
+    return MPPI_OK;
+  }
+  if (e != hipSuccess) return fail(MPPI_EDEVICE, "slot %d: %s", slot, hipGetErrorString(e));
+  *finished = true;
+  return MPPI_OK;
+}
+
+}  // namespace
+
+int mppi_jump_pool_tick(mppi_jump_pool* pl, const int32_t* ids, const float* states,
+                        const float* dist, int32_t count, int32_t iters, int32_t slot,
+                        void* stream) {
+  return guarded([&]() -> int {
+    if (!pl || !ids || !states) return fail(MPPI_EINVAL, "NULL argument");
+    if (count < 1 || count > pl->n) return fail(MPPI_EINVAL, "count=%d out of [1, %d]", count, pl->n);
+    if (iters < 1) return fail(MPPI_EINVAL, "iters=%d < 1", iters);
+    if (slot < 0 || slot >= (int)pl->slots.size()) return fail(MPPI_EINVAL, "slot %d out of range", slot);
+    PoolSlot& sl = pl->slots[slot];
+    if (sl.pending) return fail(MPPI_EINVAL, "slot %d holds results not yet taken", slot);
+    std::vector<int> order(count);
+    std::vector<char> seen(pl->n, 0);
+    for (int i = 0; i < count; ++i) {
+      const int c = ids[i];
+      if (c < 0 || c >= pl->n) return fail(MPPI_EINVAL, "controller id %d out of range", c);
+      if (seen[c]) return fail(MPPI_EINVAL, "controller %d requested twice in one tick", c);
+      if (pl->busy[c] >= 0) return fail(MPPI_EINVAL, "controller %d is in a tick in flight", c);
+      if (pl->ctxs[c]->host_iteration + (uint64_t)iters > kTwo32)
+        return fail(MPPI_EINVAL, "iteration counter of controller %d would pass 2^32", c);
+      seen[c] = 1;
+      order[i] = i;
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return pl->cost[ids[a]] > pl->cost[ids[b]]; });
+    const SlotLayout& S = pl->S;
+    char* h = pl->h_slots + (size_t)slot * S.total;
+    char* d = pl->d_slots + (size_t)slot * S.total;
+    int32_t* h_ids = reinterpret_cast<int32_t*>(h + S.ids);
+    int32_t* h_pre = reinterpret_cast<int32_t*>(h + S.prefix);
+    float* h_st = reinterpret_cast<float*>(h + S.states);
+    float* h_di = reinterpret_cast<float*>(h + S.dist);
+    int tiles = 0;
+    for (int j = 0; j < count; ++j) {
+      const int i = order[j];
+      const mppi_jump_ctx* c = pl->ctxs[ids[i]];
+      h_ids[j] = ids[i];
+      h_pre[j] = tiles;
+      tiles += c->L.nwg;
+      std::memcpy(h_st + 12 * j, states + 12 * i, sizeof(float) * c->n);
+      if (dist) std::memcpy(h_di + 4 * j, dist + 4 * i, sizeof(float) * c->m);
+    }
+    h_pre[count] = tiles;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    // one upload of ids, prefix, states and disturbances
+    HIP_TRY(hipMemcpyAsync(d, h, S.out, hipMemcpyHostToDevice, s));
+    PoolTick tk;
+    tk.ids = reinterpret_cast<const int*>(d + S.ids);
+    tk.prefix = reinterpret_cast<const int*>(d + S.prefix);
+    tk.states = reinterpret_cast<const float*>(d + S.states);
+    tk.dist = reinterpret_cast<const float*>(d + S.dist);
+    tk.out = reinterpret_cast<float*>(d + S.out);
+    tk.count = count;
+    for (int it = 0; it < iters; ++it) {
+      tk.shift = it == iters - 1 ? 1 : 0;
+      if (pl->ws)
+        pool_rollout_kernel<true><<<tiles, kBlock, pl->dyn_lds, s>>>(pl->d_desc, tk);
+      else
+        pool_rollout_kernel<false><<<tiles, kBlock, 0, s>>>(pl->d_desc, tk);
+      LAUNCH_CHECK("pool_rollout_kernel");
+    }
+    if (dist) {
+      pool_plant_kernel<<<(count + 63) / 64, 64, 0, s>>>(pl->d_desc, tk);
+      LAUNCH_CHECK("pool_plant_kernel");
+    }
+    HIP_TRY(hipMemcpyAsync(h + S.out, d + S.out, (size_t)count * kPoolOut * 4,
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(sl.done, s));
+    sl.pending = true;
+    sl.plant = dist != nullptr;
+    sl.order = std::move(order);
+    sl.ids.assign(ids, ids + count);
+    sl.count = count;
+    for (int i = 0; i < count; ++i) {
+      pl->busy[ids[i]] = slot;
+      pl->ctxs[ids[i]]->host_iteration += (uint64_t)iters;
+    }
+    return ok();
+  });
+}
+
+int mppi_jump_pool_query(mppi_jump_pool* pl, int32_t slot, int32_t* finished) {
+  return guarded([&]() -> int {
+    if (!pl || !finished) return fail(MPPI_EINVAL, "NULL argument");
+    if (slot < 0 || slot >= (int)pl->slots.size()) return fail(MPPI_EINVAL, "slot %d out of range", slot);
+    bool f = false;
+    const int rc = slot_finished(pl, slot, &f);
+    if (rc != MPPI_OK) return rc;
+    *finished = f ? 1 : 0;
+    return ok();
+  });
+}
+
+int mppi_jump_pool_results(mppi_jump_pool* pl, int32_t slot, int32_t* ids, float* u0,
+                           float* x_next, int32_t* count) {
+  return guarded([&]() -> int {
+    if (!pl || !count) return fail(MPPI_EINVAL, "NULL argument");
+    if (slot < 0 || slot >= (int)pl->slots.size()) return fail(MPPI_EINVAL, "slot %d out of range", slot);
+    PoolSlot& sl = pl->slots[slot];
+    if (!sl.pending) return fail(MPPI_EINVAL, "slot %d has no tick", slot);
+    bool f = false;
+    int rc = slot_finished(pl, slot, &f);
+    if (rc != MPPI_OK) return rc;
+    if (!f) return fail(MPPI_EINVAL, "the tick of slot %d has not finished", slot);
+    if (x_next && !sl.plant) return fail(MPPI_EINVAL, "the tick of slot %d ran no plant step", slot);
+    const float* h_out = reinterpret_cast<const float*>(pl->h_slots + (size_t)slot * pl->S.total +
+                                                        pl->S.out);
+    // a record position keeps words of earlier, larger requests beyond this
+    // request's m and n: copy only the live words and zero the rest
+    for (int j = 0; j < sl.count; ++j) {
+      const int i = sl.order[j];
+      const mppi_jump_ctx* c = pl->ctxs[sl.ids[i]];
+      if (ids) ids[i] = sl.ids[i];
+      if (u0)
+        for (int k = 0; k < 4; ++k) u0[4 * i + k] = k < c->m ? h_out[kPoolOut * j + k] : 0.f;
+      if (x_next)
+        for (int k = 0; k < 12; ++k) x_next[12 * i + k] = k < c->n ? h_out[kPoolOut * j + 4 + k] : 0.f;
+    }
+    *count = sl.count;
+    for (int c : sl.ids) pl->busy[c] = -1;
+    sl.pending = false;
+    return ok();
+  });
+}
+
+int mppi_jump_pool_destroy(mppi_jump_pool* pl) {
+  delete pl;
   return ok();
 }
 

@@ -125,6 +125,20 @@ _PROTOS = {
                                             ctypes.c_void_p]),
     "mppi_jump_batch_u0": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "mppi_jump_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "mppi_jump_pool_bytes": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+    "mppi_jump_pool_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                             ctypes.c_size_t, ctypes.c_void_p,
+                                             ctypes.POINTER(ctypes.c_void_p)]),
+    "mppi_jump_pool_tick": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.c_void_p]),
+    "mppi_jump_pool_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "mppi_jump_pool_results": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.POINTER(ctypes.c_int32)]),
+    "mppi_jump_pool_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "mppi_jump_philox": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                         ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "mppi_jump_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),

@@ -149,3 +149,62 @@ def random_controllers(count, seed=42):
         cfg.update(seed=42 + i, controller_id=i)
         out.append((cfg, x0))
     return out
+
+
+def serving_controllers(count=1024, seed=4):
+    """Resident controller set of the serving form: an exact half/half
+    cartpole / quadrotor split in shuffled order, K from {1024..8192}, T from
+    [50, 150], nu from [0, 10] /s, random initial states, per-controller
+    seed and controller id."""
+    g = np.random.default_rng(seed)
+    kinds = np.array([1] * (count // 2) + [2] * (count - count // 2))
+    g.shuffle(kinds)
+    out = []
+    for i, d in enumerate(kinds):
+        K = int(g.choice([1024, 2048, 4096, 8192]))
+        T = int(g.integers(50, 151))
+        nu = float(g.uniform(0.0, 10.0))
+        if d == 1:
+            cfg = cartpole(K=K, T=T, nu=nu)
+            x0 = np.array([g.uniform(-1, 1), 0.0, g.uniform(-math.pi, math.pi), 0.0],
+                          dtype=np.float32)
+        else:
+            cfg = quadrotor(K=K, T=T, nu=nu)
+            x0 = np.zeros(12, dtype=np.float32)
+            x0[0:2] = g.uniform(-1, 1, size=2)
+            x0[2] = g.uniform(0.5, 1.5)
+            x0[6:9] = g.uniform(-0.1, 0.1, size=3)
+        cfg.update(seed=1000 + i, controller_id=i)
+        out.append((cfg, x0))
+    return out
+
+
+def serving_arrivals(rate, duration, count, seed=9):
+    """Poisson request stream: arrival times (s, exponential gaps of mean
+    1/rate) over [0, duration) and, for each, a uniformly chosen controller."""
+    g = np.random.default_rng(seed)
+    n = int(rate * duration * 1.2) + 64
+    t = np.cumsum(g.exponential(1.0 / rate, size=n))
+    while t[-1] < duration:
+        t = np.concatenate([t, t[-1] + np.cumsum(g.exponential(1.0 / rate, size=n))])
+    t = t[t < duration]
+    return t, g.integers(0, count, size=len(t)).astype(np.int32)
+
+
+def serving_disturbances(cfg, steps, seed):
+    """Plant disturbances of one served controller, [steps, 4] fp32, added to
+    its control channels: N(0, sigma_j^2) per channel plus, where the model's
+    jumps enter the control channels, a Poisson(nu dt) number of
+    N(0, sigma_J^2) jumps (one count per step).  The quadrotor's jumps are a
+    world-frame gust, which this plant step does not model, so its plant gets
+    the Gaussian part only."""
+    n, m, q = DIMS[cfg["dynamics"]]
+    g = np.random.default_rng(seed)
+    sig = np.asarray(cfg["sigma"][:m], dtype=np.float64)
+    d = np.zeros((steps, 4))
+    d[:, :m] = sig * g.standard_normal((steps, m))
+    if cfg["dynamics"] != 2:
+        cnt = g.poisson(cfg["nu"] * cfg["dt"], size=steps)
+        sj = np.asarray(cfg["sigma_J"][:m], dtype=np.float64)
+        d[:, :m] += sj * np.sqrt(cnt)[:, None] * g.standard_normal((steps, m))
+    return d.astype(np.float32)

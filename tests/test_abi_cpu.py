@@ -125,3 +125,49 @@ def test_count_tables_equal_the_oracle(nu, law, dt):
     ref = noise.count_thresholds(a, law)
     assert lib_th[:len(ref)] == ref
     assert all(v == 2**32 for v in lib_th[len(ref):])
+
+
+def test_pool_and_batch_entry_points_reject_null_arguments():
+    import ctypes
+    L = native.lib()
+    EINVAL = native.C["MPPI_EINVAL"]
+    d, h = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.mppi_jump_pool_bytes(None, 0, 1, ctypes.byref(d), ctypes.byref(h)) == EINVAL
+    assert L.mppi_jump_pool_bytes(None, 1, 0, ctypes.byref(d), ctypes.byref(h)) == EINVAL
+    assert L.mppi_jump_pool_tick(None, None, None, None, 1, 1, 0, None) == EINVAL
+    f = ctypes.c_int32()
+    assert L.mppi_jump_pool_query(None, 0, ctypes.byref(f)) == EINVAL
+    assert L.mppi_jump_pool_results(None, 0, None, None, None, ctypes.byref(f)) == EINVAL
+    assert L.mppi_jump_batch_scratch_bytes(None, 1, ctypes.byref(d)) == EINVAL
+
+
+def test_serving_workload_recipe():
+    cs = workloads.serving_controllers(1024)
+    kinds = [c["dynamics"] for c, _ in cs]
+    assert kinds.count(1) == kinds.count(2) == 512
+    assert {c["K"] for c, _ in cs} == {1024, 2048, 4096, 8192}
+    assert min(c["T"] for c, _ in cs) >= 50 and max(c["T"] for c, _ in cs) <= 150
+    assert len({c["controller_id"] for c, _ in cs}) == 1024
+    t, ids = workloads.serving_arrivals(20000.0, 2.0, 1024, seed=9)
+    gaps = np.diff(t)
+    assert abs(gaps.mean() - 5e-5) < 2e-6 and abs(gaps.std() / gaps.mean() - 1.0) < 0.03
+    assert t.max() < 2.0 and ids.min() >= 0 and ids.max() < 1024
+    d = workloads.serving_disturbances(workloads.quadrotor(), 1000, seed=1)
+    assert d.shape == (1000, 4) and abs(d.std() - 0.5) < 0.05
+    d = workloads.serving_disturbances(workloads.cartpole_mpc(), 20000, seed=1)
+    assert not d[:, 1:].any()
+    # variance 1 + nu dt sigma_J^2 = 1 + 0.1 * 100
+    assert abs(d[:, 0].var() / 11.0 - 1.0) < 0.1
+
+
+def test_admission_by_footprint():
+    from paper_1807_06108_amd import serving
+    cfgs = [c for c, _ in workloads.serving_controllers(64)]
+    need = [serving.footprint_bytes(c) for c in cfgs]
+    assert need == [native.workspace_bytes(c) for c in cfgs]
+    ok, refused, used = serving.admit(cfgs, sum(need))
+    assert ok == list(range(64)) and not refused and used == sum(need)
+    cap = sum(need[:10]) + 1
+    ok, refused, used = serving.admit(cfgs, cap)
+    assert ok[:10] == list(range(10)) and used <= cap
+    assert sorted(ok + refused) == list(range(64))
