@@ -17,6 +17,12 @@ The JSON line also carries
                    its average duration comes from HIP events on its own
                    stream, sampled on every PROFILE_EVERY-th control step of
                    the timed region (events on every launch would perturb it),
+  batched          256 uneven controllers advanced by one graph-replayed launch
+                   per tick against the same controllers launched one by one,
+  serving          1024 resident controllers under Poisson arrivals at 20k
+                   MPC-step requests/s: p50/p99 latency (arrival to u0 on the
+                   host) of pooled ticks against per-controller launches, and
+                   the capacity of each back end,
   cpu_baseline     the FP64 oracle on a bounded sample of the same loop.
 """
 
@@ -48,13 +54,22 @@ CSRC = os.path.join(ROOT, "paper_1807_06108_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rollout_traffic.json")
 
 
+# sources that define the plain rollout kernels and their launch
+KERNEL_SOURCES = ("kernels.hpp", "rollout_ws.hpp", "rng.hpp", "models.hpp", "reduce.hpp",
+                  "mppi_jump.hip")
+
+
 def source_hash():
-    """Digest of the kernel sources (ties counter results to a kernel)."""
+    """Digest of the rollout kernel sources (ties counter results to a kernel)."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
+    for name in KERNEL_SOURCES:
         with open(os.path.join(CSRC, name), "rb") as f:
             h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
+
+
+def progress(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def measured_traffic(workload):
@@ -151,6 +166,53 @@ def batched_measure(n_ctl, ticks, warmup, seed=42):
             "speedup": batched["value"] / plain["value"]}
 
 
+def serving_measure(rate, seconds, warm, n_ctl=1024, seed=4):
+    """Serving form against plain per-controller launches under the same
+    request stream: n_ctl resident controllers (half cartpole, half
+    quadrotor, K in {1024..8192}, T in [50, 150]), Poisson arrivals at `rate`
+    requests/s, each one MPC step (1 iteration + shift) from the
+    controller's own plant state, plant stepped on the device.  Latency is
+    arrival to u_0 on the host.  Then the capacity of each back end: the
+    throughput it sustains under an offered rate above it."""
+    from paper_1807_06108_amd import autotune, serving, workloads
+    cs = workloads.serving_controllers(n_ctl, seed=seed)
+    cfgs = [c for c, _ in cs]
+    x0s = [x for _, x in cs]
+    dist = [workloads.serving_disturbances(c, 256, seed=2000 + i) for i, c in enumerate(cfgs)]
+    import torch
+    sched, report = autotune.choose_schedule(
+        cfgs, [torch.tensor(x, device="cuda") for x in x0s], subset=4)
+
+    def run(backend, schedule, r, secs, w):
+        t, ids = workloads.serving_arrivals(r, secs + w, n_ctl, seed=9)
+        srv = serving.Server(cfgs, x0s, dist, hbm_cap_bytes=64 << 30, max_inflight=4,
+                             backend=backend, schedule=schedule)
+        res = srv.run(t, ids, warmup_s=w)
+        res.update(admitted=len(srv.admitted), admitted_gb=srv.admitted_bytes / 2**30)
+        srv.close()
+        torch.cuda.synchronize()
+        return res
+
+    out = {"controllers": n_ctl, "rate_per_s": rate, "measured_s": seconds, "warmup_s": warm,
+           "hbm_cap_gb": 64, "schedule": {1: "lane", 2: "ws"}[int(sched)],
+           "autotune_ms": report["timings_ms"]}
+    progress("serving: pooled ticks at %.0f requests/s" % rate)
+    out["pool"] = run("pool", sched, rate, seconds, warm)
+    progress("serving: per-controller launches at %.0f requests/s" % rate)
+    out["plain"] = run("plain", sched, rate, seconds, warm)
+    out["p99_ratio_plain_over_pool"] = out["plain"]["latency_ms"]["p99"] / out["pool"]["latency_ms"]["p99"]
+    cap = {}
+    for name, backend, schedule, offered in (("pool_lane", "pool", 1, 250e3),
+                                             ("pool_ws", "pool", 2, 250e3),
+                                             ("plain", "plain", sched, 40e3)):
+        progress("serving capacity: %s" % name)
+        r = run(backend, schedule, offered, 1.0, 0.5)
+        cap[name] = {"offered_per_s": offered, "requests_per_s": r["requests_per_s"],
+                     "rollout_steps_per_s": r["rollout_steps_per_s"]}
+    out["capacity"] = cap
+    return out
+
+
 def calibrate_copy(nbytes=256 << 20, reps=4):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -182,6 +244,10 @@ def main():
     ap.add_argument("--batched-controllers", type=int, default=256)
     ap.add_argument("--batched-ticks", type=int, default=20,
                     help="0 skips the batched-form comparison")
+    ap.add_argument("--serving-seconds", type=float, default=10.0,
+                    help="measured seconds of the serving comparison (0 skips it)")
+    ap.add_argument("--serving-warmup", type=float, default=2.0)
+    ap.add_argument("--serving-rate", type=float, default=20000.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the method's parallel axis (samples) fits one "
@@ -298,9 +364,16 @@ def main():
                      "slots_per_sample_step": ALG_SLOTS[dyn],
                      "fp32_tflops": flops / 1e12, "fp32_frac": flops / FP32_PEAK},
     }
+    progress("plain form done: %.4f ms per control step" % (wall / args.steps * 1e3))
     if args.batched_ticks > 0:
+        progress("batched form")
         line["batched"] = batched_measure(args.batched_controllers, args.batched_ticks, 3)
+    if args.serving_seconds > 0:
+        progress("serving form (about %.0f s)" % (2 * (args.serving_seconds + args.serving_warmup) + 5))
+        line["serving"] = serving_measure(args.serving_rate, args.serving_seconds,
+                                          args.serving_warmup)
     if not args.no_cpu_baseline:
+        progress("oracle on the host cores (about %.0f s)" % args.cpu_budget)
         line["cpu_baseline"] = cpu_baseline(cfg, x0, U0, iters,
                                             dist[args.warmup:].astype(np.float64),
                                             args.cpu_budget)

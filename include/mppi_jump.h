@@ -336,10 +336,13 @@ int mppi_jump_plant_step(mppi_jump_ctx* ctx, float* d_x, const float* d_u,
 int mppi_jump_philox(const uint32_t* d_counters, uint32_t key0, uint32_t key1,
                      uint32_t* d_out, int64_t n, void* stream);
 
-/* Timing of the rollout kernel: when enabled, every rollout launch is
- * bracketed by HIP events on its own stream.  profile_read synchronises on
- * the recorded events and returns the summed duration (ms) and the launch
- * count, then clears them.  At most 4096 launches are kept. */
+/* Timing of the rollout kernel: when enabled, rollout launches are bracketed
+ * by HIP events on their stream: the fused launches of one mppi_jump_step /
+ * mppi_jump_control_step call (back-to-back rollout kernels) by one event
+ * pair, any other rollout launch by its own.  profile_read synchronises on
+ * the recorded events and returns the summed bracketed duration (ms) and the
+ * number of rollout launches inside the brackets, then clears them.  At most
+ * 4096 brackets are kept. */
 int mppi_jump_profile(mppi_jump_ctx* ctx, int32_t enable);
 int mppi_jump_profile_read(mppi_jump_ctx* ctx, double* total_ms, int64_t* launches);
 

@@ -27,14 +27,15 @@ struct BatchTile {
 };
 
 template <bool WS>
-__device__ __forceinline__ void batch_tile(const BatchDesc& d, const ShiftArgs& sh, int wg) {
+__device__ __forceinline__ void batch_tile(const BatchDesc& d, const float* x0, const ShiftArgs& sh,
+                                           int wg) {
   const int sel = d.dyn * 4 + d.jumps * 2 + (d.form == MPPI_COST_SO ? 1 : 0);
 #define MPPI_BATCH_CASE(DYN, J, F)                                                            \
   case DYN * 4 + J * 2 + (F == MPPI_COST_SO ? 1 : 0):                                       \
     if constexpr (WS)                                                                         \
-      rollout_ws_tile<DYN, J, false, F, true, 4>(d.p, d.b, d.x0, d.b.U, d.R, sh, wg, d.nwg); \
+      rollout_ws_tile<DYN, J, false, F, true, 4>(d.p, d.b, x0, d.b.U, d.R, sh, wg, d.nwg);   \
     else                                                                                      \
-      rollout_lane_tile<DYN, J, false, F, true>(d.p, d.b, d.x0, d.b.U, d.R, sh, wg, d.nwg);  \
+      rollout_lane_tile<DYN, J, false, F, true>(d.p, d.b, x0, d.b.U, d.R, sh, wg, d.nwg);    \
     break;
   switch (sel) {
     MPPI_BATCH_CASE(MPPI_DYN_LINEAR, 0, MPPI_COST_IT)
@@ -66,7 +67,7 @@ __global__ __launch_bounds__(256) void batch_rollout_kernel(const BatchDesc* __r
   sh.u0_out = d.u0_out;
   sh.m = d.m;
   sh.u_init = d.u_init;
-  batch_tile<WS>(d, sh, tl.wg);
+  batch_tile<WS>(d, d.x0, sh, tl.wg);
 }
 
 }  // namespace mppi
@@ -108,14 +109,13 @@ template <bool WS>
 __global__ __launch_bounds__(256) void pool_rollout_kernel(const BatchDesc* __restrict__ descs,
                                                            const PoolTick tick) {
   const int i = find_request(tick.prefix, tick.count, blockIdx.x);
-  BatchDesc d = descs[tick.ids[i]];
-  d.x0 = tick.states + 12 * i;
+  const BatchDesc& d = descs[tick.ids[i]];
   ShiftArgs sh;
   sh.on = tick.shift;
   sh.u0_out = tick.out + kPoolOut * i;
   sh.m = d.m;
   sh.u_init = d.u_init;
-  batch_tile<WS>(d, sh, blockIdx.x - tick.prefix[i]);
+  batch_tile<WS>(d, tick.states + 12 * i, sh, blockIdx.x - tick.prefix[i]);
 }
 
 template <int DYN>

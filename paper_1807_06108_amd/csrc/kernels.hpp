@@ -129,39 +129,67 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
                                                  bool active, int R, const ShiftArgs sh, int wg,
                                                  int nwg) {
   constexpr int NW = NT / 64;
+  constexpr int RPP = NT / 4;  // eps tile rows per pass, four threads per row
   __shared__ double lds[NW];
   __shared__ double e_lds[SPW];
   __shared__ double stage[FUSED ? kStageRows : 1];
   __shared__ double sc_lds[FUSED ? kFusedMaxWg : 1];
+  __shared__ double seg_lds[FUSED ? NT : 1];
+  __shared__ double bc[3];
   __shared__ int is_last;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool fin = active && isfinite(Sd);
-  const double rho_wg = block_min<NW>(fin ? Sd : INFINITY, lds);
-  const double e = fin ? exp(-(Sd - rho_wg) / p.lam_d) : 0.0;
   const int k0 = wg * SPW;
-  if (active) b.E[k0 + threadIdx.x] = e;
-  if (threadIdx.x < SPW) e_lds[threadIdx.x] = e;
-  const double eta_wg = block_sum<NW>(e, lds);
-  const double nfin = block_sum<NW>(fin ? 1.0 : 0.0, lds);
+  // statistics of the workgroup; wavefront 0 ends up holding them
+  double rho_wg = INFINITY, eta_wg = 0.0, nfin = 0.0;
+  if constexpr (SPW == 64) {
+    // the costs live in wavefront 0: wavefront reductions, no barriers
+    if (wave == 0) {
+      rho_wg = wave_min(fin ? Sd : INFINITY);
+      const double e = fin ? exp(-(Sd - rho_wg) / p.lam_d) : 0.0;
+      if (active) b.E[k0 + lane] = e;
+      e_lds[lane] = e;
+      eta_wg = wave_sum(e);
+      nfin = (double)__popcll(__ballot(fin));
+    }
+    __syncthreads();  // e_lds
+  } else {
+    rho_wg = block_min<NW>(fin ? Sd : INFINITY, lds);
+    const double e = fin ? exp(-(Sd - rho_wg) / p.lam_d) : 0.0;
+    if (active) b.E[k0 + threadIdx.x] = e;
+    if (threadIdx.x < SPW) e_lds[threadIdx.x] = e;
+    eta_wg = block_sum<NW>(e, lds);
+    nfin = block_sum<NW>(fin ? 1.0 : 0.0, lds);  // its barriers publish e_lds
+  }
   if constexpr (FUSED) {
     // the workgroup's own eps tile (written earlier in this kernel by its
-    // threads, visible after the barriers of the reductions), reduced by all
-    // threads into LDS, stored by wavefront 0
+    // threads, visible after the barriers above): row r is reduced by four
+    // consecutive threads over a quarter of the samples each, in sample
+    // order, the quarters added as (q0 + q1) + (q2 + q3); the row sums are
+    // staged in LDS and stored by wavefront 0
+    constexpr int SQ = SPW / 4;  // samples per thread
+    const int q = threadIdx.x & 3, i4 = threadIdx.x >> 2;
     for (int base = 0; base < R; base += kStageRows) {
       const int nrow = min(kStageRows, R - base);
-      for (int i = threadIdx.x; i < nrow; i += NT) {
-        const float4* row =
-            reinterpret_cast<const float4*>(b.eps + (size_t)(base + i) * p.Ks + k0);
+      for (int i0 = 0; i0 < nrow; i0 += RPP) {
+        const int i = i0 + i4;
         double acc = 0.0;
-#pragma unroll 8
-        for (int j = 0; j < SPW / 4; ++j) {
-          const float4 v = row[j];
-          acc += e_lds[4 * j] * (double)v.x;
-          acc += e_lds[4 * j + 1] * (double)v.y;
-          acc += e_lds[4 * j + 2] * (double)v.z;
-          acc += e_lds[4 * j + 3] * (double)v.w;
+        if (i < nrow) {
+          const float4* row =
+              reinterpret_cast<const float4*>(b.eps + (size_t)(base + i) * p.Ks + k0 + q * SQ);
+          const double* ew = e_lds + q * SQ;
+#pragma unroll
+          for (int j = 0; j < SQ / 4; ++j) {
+            const float4 v = row[j];
+            acc += ew[4 * j] * (double)v.x;
+            acc += ew[4 * j + 1] * (double)v.y;
+            acc += ew[4 * j + 2] * (double)v.z;
+            acc += ew[4 * j + 3] * (double)v.w;
+          }
         }
-        stage[i] = acc;
+        acc += __shfl_xor(acc, 1, 64);
+        acc += __shfl_xor(acc, 2, 64);
+        if (q == 0 && i < nrow) stage[i] = acc;
       }
       __syncthreads();
       if (wave == 0)
@@ -184,40 +212,131 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
   __syncthreads();
   if (!is_last) return;
   __threadfence();
-  double m = INFINITY;
-  for (int j = threadIdx.x; j < nwg; j += NT)
-    if (b.part[j].nfin > 0) m = fmin(m, b.part[j].rho);
-  const double rho = block_min<NW>(m, lds);
-  double eta = 0.0, cnt = 0.0;
-  for (int j = threadIdx.x; j < nwg; j += NT) {
-    const WgPartial q = b.part[j];
-    const double sc = (q.nfin > 0) ? exp(-(q.rho - rho) / p.lam_d) : 0.0;
-    b.scale[j] = sc;
-    if constexpr (FUSED) sc_lds[j] = sc;
-    eta += q.eta * sc;
-    cnt += q.nfin;
+  // First pass of the fused update (rows [0, Rp)): when there are threads
+  // to spare, each row's partials are split into S contiguous segments, one
+  // thread each.  The segment's first kPre partials and the row's U are
+  // loaded now, so that their latency overlaps the statistics below.
+  constexpr int kPre = 8;
+  int Rp = 1, S = 1, L = 0, seg = 0, rr = 0, j0 = 0, j1 = 0;
+  double wpre[kPre];
+  float uold = 0.f;
+  if constexpr (FUSED) {
+    Rp = min(NT, R);
+    S = max(1, min(NT / Rp, (nwg + kPre - 1) / kPre));
+    L = (nwg + S - 1) / S;
+    seg = threadIdx.x / Rp;
+    rr = threadIdx.x - seg * Rp;
+    j0 = seg < S ? seg * L : 0;
+    j1 = seg < S ? min(nwg, j0 + L) : 0;
+    const double* wr = b.wpart + (size_t)rr * nwg;
+#pragma unroll
+    for (int q = 0; q < kPre; ++q) wpre[q] = j0 + q < j1 ? wr[j0 + q] : 0.0;
+    if (seg == 0) uold = b.U[rr];
   }
-  eta = block_sum<NW>(eta, lds);
-  cnt = block_sum<NW>(cnt, lds);  // its barrier also publishes sc_lds to the block
+  // combination (wavefront 0): rho = min of the workgroup minima, the
+  // rescales exp(-(rho_wg - rho)/lambda), eta and the finite count; the
+  // first 64 partials stay in registers between the two passes
+  if (wave == 0) {
+    const bool h = lane < nwg;
+    const double hrho = h ? b.part[lane].rho : INFINITY;
+    const double heta = h ? b.part[lane].eta : 0.0;
+    const int hfin = h ? b.part[lane].nfin : 0;
+    double m = hfin > 0 ? hrho : INFINITY;
+    for (int j = lane + 64; j < nwg; j += 64)
+      if (b.part[j].nfin > 0) m = fmin(m, b.part[j].rho);
+    const double rho = wave_min(m);
+    double eta = 0.0, cnt = 0.0;
+    if (h) {
+      const double sc = hfin > 0 ? exp(-(hrho - rho) / p.lam_d) : 0.0;
+      b.scale[lane] = sc;
+      if constexpr (FUSED) sc_lds[lane] = sc;
+      eta += heta * sc;
+      cnt += hfin;
+    }
+    for (int j = lane + 64; j < nwg; j += 64) {
+      const WgPartial q = b.part[j];
+      const double sc = (q.nfin > 0) ? exp(-(q.rho - rho) / p.lam_d) : 0.0;
+      b.scale[j] = sc;
+      if constexpr (FUSED) sc_lds[j] = sc;
+      eta += q.eta * sc;
+      cnt += q.nfin;
+    }
+    eta = wave_sum(eta);
+    cnt = wave_sum(cnt);
+    if (lane == 0) {
+      bc[0] = rho;
+      bc[1] = eta;
+      bc[2] = cnt;
+    }
+  }
+  __syncthreads();  // bc and sc_lds
+  const double rho = bc[0], eta = bc[1], cnt = bc[2];
   const bool ok = cnt > 0;
   if constexpr (FUSED) {
-    // one thread per row; four independent accumulators keep loads in
-    // flight; the summation order is fixed
+    // U[r] += alpha / eta * sum_wg scale_wg P[r][wg]: each segment is summed
+    // with four accumulators in a fixed pattern, the segment sums in segment
+    // order
     if (ok) {
       const double f = (double)p.alpha / eta;
-      for (int r = threadIdx.x; r < R; r += NT) {
-        const double* wr = b.wpart + (size_t)r * nwg;
-        double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
-        int j = 0;
-#pragma unroll 4
-        for (; j + 4 <= nwg; j += 4) {
-          d0 += sc_lds[j] * wr[j];
-          d1 += sc_lds[j + 1] * wr[j + 1];
-          d2 += sc_lds[j + 2] * wr[j + 2];
-          d3 += sc_lds[j + 3] * wr[j + 3];
+      for (int base = 0; base < R; base += NT) {
+        const bool first = base == 0;
+        if (!first) {
+          Rp = min(NT, R - base);
+          S = max(1, min(NT / Rp, (nwg + kPre - 1) / kPre));
+          L = (nwg + S - 1) / S;
+          seg = threadIdx.x / Rp;
+          rr = threadIdx.x - seg * Rp;
+          j0 = seg < S ? seg * L : 0;
+          j1 = seg < S ? min(nwg, j0 + L) : 0;
         }
-        for (; j < nwg; ++j) d0 += sc_lds[j] * wr[j];
-        b.U[r] = (float)((double)b.U[r] + f * ((d0 + d1) + (d2 + d3)));
+        double acc = 0.0;
+        if (seg < S) {
+          const double* wr = b.wpart + (size_t)(base + rr) * nwg;
+          double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+          int j = j0;
+          if (first) {
+            // the preloaded groups of four (kPre is a multiple of four)
+#pragma unroll
+            for (int q = 0; q < kPre; q += 4) {
+              if (j + 4 <= j1) {
+                d0 += sc_lds[j] * wpre[q];
+                d1 += sc_lds[j + 1] * wpre[q + 1];
+                d2 += sc_lds[j + 2] * wpre[q + 2];
+                d3 += sc_lds[j + 3] * wpre[q + 3];
+                j += 4;
+              }
+            }
+            if (j1 - j0 < kPre) {
+              // the segment's tail is preloaded too (constant register
+              // indices: the q loop is unrolled)
+              const int jt = j;
+#pragma unroll
+              for (int q = 0; q < kPre; ++q)
+                if (j0 + q >= jt && j0 + q < j1) d0 += sc_lds[j0 + q] * wpre[q];
+              j = j1;
+            }
+          }
+#pragma unroll 4
+          for (; j + 4 <= j1; j += 4) {
+            d0 += sc_lds[j] * wr[j];
+            d1 += sc_lds[j + 1] * wr[j + 1];
+            d2 += sc_lds[j + 2] * wr[j + 2];
+            d3 += sc_lds[j + 3] * wr[j + 3];
+          }
+          for (; j < j1; ++j) d0 += sc_lds[j] * wr[j];
+          acc = (d0 + d1) + (d2 + d3);
+        }
+        if (S > 1) {
+          seg_lds[threadIdx.x] = acc;
+          __syncthreads();
+          if (seg == 0)
+            for (int s2 = 1; s2 < S; ++s2) acc += seg_lds[s2 * Rp + rr];
+        }
+        if (seg == 0) {
+          const float uo = first ? uold : b.U[base + rr];
+          b.U[base + rr] = (float)((double)uo + f * acc);
+        }
+        if (S > 1) __syncthreads();
       }
     }
     if (sh.on) {

@@ -267,7 +267,11 @@ struct mppi_jump_ctx {
   uint64_t th64[MPPI_JUMP_MAX_LEVELS];
   uint64_t host_iteration;  // iterations enqueued so far (range check only)
   bool profiling = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  struct Bracket {
+    hipEvent_t e0, e1;
+    int launches;
+  };
+  std::vector<Bracket> events;  // one pair per bracketed span of rollout launches
   size_t events_used = 0;
 };
 
@@ -310,19 +314,35 @@ int launch_rollout_dyn(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, bool 
              : launch_rollout_form<DYN, false, false>(ctx, x0, s, fused, sh);
 }
 
+// Timing brackets: an event pair around a span of back-to-back rollout
+// launches (one launch, or all fused launches of one entry-point call).
+int bracket_begin(mppi_jump_ctx* ctx, hipStream_t s) {
+  if (!ctx->profiling) return MPPI_OK;
+  if (ctx->events_used >= 4096) return fail(MPPI_EINVAL, "profiling buffer full (4096 spans)");
+  if (ctx->events_used == ctx->events.size()) {
+    mppi_jump_ctx::Bracket br{nullptr, nullptr, 0};
+    HIP_TRY(hipEventCreate(&br.e0));
+    HIP_TRY(hipEventCreate(&br.e1));
+    ctx->events.push_back(br);
+  }
+  HIP_TRY(hipEventRecord(ctx->events[ctx->events_used].e0, s));
+  return MPPI_OK;
+}
+
+int bracket_end(mppi_jump_ctx* ctx, hipStream_t s, int launches) {
+  if (!ctx->profiling) return MPPI_OK;
+  HIP_TRY(hipEventRecord(ctx->events[ctx->events_used].e1, s));
+  ctx->events[ctx->events_used].launches = launches;
+  ctx->events_used++;
+  return MPPI_OK;
+}
+
+// own_bracket: time this launch on its own (else the caller brackets a span)
 int launch_rollout(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, bool fused,
-                   const ShiftArgs& sh = ShiftArgs{}) {
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (ctx->profiling) {
-    if (ctx->events_used >= 4096) return fail(MPPI_EINVAL, "profiling buffer full (4096 launches)");
-    if (ctx->events_used == ctx->events.size()) {
-      HIP_TRY(hipEventCreate(&e0));
-      HIP_TRY(hipEventCreate(&e1));
-      ctx->events.emplace_back(e0, e1);
-    }
-    e0 = ctx->events[ctx->events_used].first;
-    e1 = ctx->events[ctx->events_used].second;
-    HIP_TRY(hipEventRecord(e0, s));
+                   const ShiftArgs& sh = ShiftArgs{}, bool own_bracket = true) {
+  if (own_bracket) {
+    const int rb = bracket_begin(ctx, s);
+    if (rb != MPPI_OK) return rb;
   }
   int rc;
   switch (ctx->cfg.dynamics) {
@@ -331,11 +351,7 @@ int launch_rollout(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, bool fuse
     default: rc = launch_rollout_dyn<MPPI_DYN_QUADROTOR>(ctx, x0, s, fused, sh); break;
   }
   if (rc != MPPI_OK) return rc;
-  if (ctx->profiling) {
-    HIP_TRY(hipEventRecord(e1, s));
-    ctx->events_used++;
-  }
-  return MPPI_OK;
+  return own_bracket ? bracket_end(ctx, s, 1) : MPPI_OK;
 }
 
 int launch_update(mppi_jump_ctx* ctx, hipStream_t s) {
@@ -478,14 +494,23 @@ int mppi_jump_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, void* s
     if (ctx->host_iteration + (uint64_t)iters > kTwo32)
       return fail(MPPI_EINVAL, "iteration counter would pass 2^32");
     const hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool span = ctx->L.fused;  // fused launches run back to back: one bracket
+    if (span) {
+      const int rb = bracket_begin(ctx, s);
+      if (rb != MPPI_OK) return rb;
+    }
     for (int i = 0; i < iters; ++i) {
-      int rc = launch_rollout(ctx, d_x0, s, ctx->L.fused);
+      int rc = launch_rollout(ctx, d_x0, s, ctx->L.fused, ShiftArgs{}, !span);
       if (rc != MPPI_OK) return rc;
       if (!ctx->L.fused) {
         rc = launch_update(ctx, s);
         if (rc != MPPI_OK) return rc;
       }
       ctx->host_iteration += 1;
+    }
+    if (span) {
+      const int rb = bracket_end(ctx, s, iters);
+      if (rb != MPPI_OK) return rb;
     }
     return ok();
   });
@@ -504,6 +529,8 @@ int mppi_jump_control_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters,
       if (rc != MPPI_OK) return rc;
       return mppi_jump_shift(ctx, d_u0_out, stream);
     }
+    int rc = bracket_begin(ctx, s);
+    if (rc != MPPI_OK) return rc;
     for (int i = 0; i < iters; ++i) {
       ShiftArgs sh{};
       if (i == iters - 1) {
@@ -512,11 +539,12 @@ int mppi_jump_control_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters,
         sh.m = ctx->m;
         sh.u_init = u_init4(ctx->cfg);
       }
-      const int rc = launch_rollout(ctx, d_x0, s, true, sh);
+      rc = launch_rollout(ctx, d_x0, s, true, sh, false);
       if (rc != MPPI_OK) return rc;
       ctx->host_iteration += 1;
     }
-    return ok();
+    rc = bracket_end(ctx, s, iters);
+    return rc == MPPI_OK ? ok() : rc;
   });
 }
 
@@ -1073,8 +1101,8 @@ int mppi_jump_pool_destroy(mppi_jump_pool* pl) {
 int mppi_jump_destroy(mppi_jump_ctx* ctx) {
   if (!ctx) return ok();
   for (auto& e : ctx->events) {
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
+    (void)hipEventDestroy(e.e0);
+    (void)hipEventDestroy(e.e1);
   }
   delete ctx;
   return ok();
@@ -1132,14 +1160,16 @@ int mppi_jump_profile_read(mppi_jump_ctx* ctx, double* total_ms, int64_t* launch
   return guarded([&]() -> int {
     if (!ctx || !total_ms || !launches) return fail(MPPI_EINVAL, "NULL argument");
     double tot = 0.0;
+    int64_t n = 0;
     for (size_t i = 0; i < ctx->events_used; ++i) {
-      HIP_TRY(hipEventSynchronize(ctx->events[i].second));
+      HIP_TRY(hipEventSynchronize(ctx->events[i].e1));
       float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, ctx->events[i].first, ctx->events[i].second));
+      HIP_TRY(hipEventElapsedTime(&ms, ctx->events[i].e0, ctx->events[i].e1));
       tot += ms;
+      n += ctx->events[i].launches;
     }
     *total_ms = tot;
-    *launches = (int64_t)ctx->events_used;
+    *launches = n;
     ctx->events_used = 0;
     return ok();
   });
