@@ -160,10 +160,18 @@ def batched_measure(n_ctl, ticks, warmup, seed=42):
     for _ in range(warmup):
         plain_tick()
     plain = timed(plain_tick, ticks)
+    # VALU issue of one tick against the chip's peak (the per-sample-step
+    # slot counts of each controller's model)
+    slots = sum(ALG_SLOTS[c["dynamics"]] * c["K"] * c["T"] for c in cfgs)
+    achieved = slots / (batched["ms_per_tick"] * 1e-3)
     return {"controllers": n_ctl, "rollout_steps_per_tick": work,
             "schedule": {1: "lane", 2: "ws"}[sched], "autotune_ms": report["timings_ms"],
             "batched_graph": batched, "plain_sequential": plain,
-            "speedup": batched["value"] / plain["value"]}
+            "speedup": batched["value"] / plain["value"],
+            "roofline": {"bound": "alu", "achieved": achieved / 1e12,
+                         "peak": VALU_PEAK_SLOTS / 1e12, "unit": "T VALU-slot/s",
+                         "frac": achieved / VALU_PEAK_SLOTS,
+                         "what": "issue slots of every controller's sample-steps per tick / tick time"}}
 
 
 def serving_measure(rate, seconds, warm, n_ctl=1024, seed=4):

@@ -233,27 +233,40 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
     for (int q = 0; q < kPre; ++q) wpre[q] = j0 + q < j1 ? wr[j0 + q] : 0.0;
     if (seg == 0) uold = b.U[rr];
   }
-  // combination (wavefront 0): rho = min of the workgroup minima, the
-  // rescales exp(-(rho_wg - rho)/lambda), eta and the finite count; the
-  // first 64 partials stay in registers between the two passes
-  if (wave == 0) {
-    const bool h = lane < nwg;
-    const double hrho = h ? b.part[lane].rho : INFINITY;
-    const double heta = h ? b.part[lane].eta : 0.0;
-    const int hfin = h ? b.part[lane].nfin : 0;
-    double m = hfin > 0 ? hrho : INFINITY;
-    for (int j = lane + 64; j < nwg; j += 64)
-      if (b.part[j].nfin > 0) m = fmin(m, b.part[j].rho);
-    const double rho = wave_min(m);
-    double eta = 0.0, cnt = 0.0;
-    if (h) {
-      const double sc = hfin > 0 ? exp(-(hrho - rho) / p.lam_d) : 0.0;
-      b.scale[lane] = sc;
-      if constexpr (FUSED) sc_lds[lane] = sc;
-      eta += heta * sc;
-      cnt += hfin;
+  // combination: rho = min of the workgroup minima, the rescales
+  // exp(-(rho_wg - rho)/lambda), eta and the finite count.  Up to 64
+  // partials: wavefront 0 alone, one per lane held in registers; more: the
+  // whole workgroup with block reductions.
+  if (nwg <= 64) {
+    if (wave == 0) {
+      const bool h = lane < nwg;
+      const double hrho = h ? b.part[lane].rho : INFINITY;
+      const double heta = h ? b.part[lane].eta : 0.0;
+      const int hfin = h ? b.part[lane].nfin : 0;
+      const double rho = wave_min(hfin > 0 ? hrho : INFINITY);
+      double eta = 0.0, cnt = 0.0;
+      if (h) {
+        const double sc = hfin > 0 ? exp(-(hrho - rho) / p.lam_d) : 0.0;
+        b.scale[lane] = sc;
+        if constexpr (FUSED) sc_lds[lane] = sc;
+        eta = heta * sc;
+        cnt = hfin;
+      }
+      eta = wave_sum(eta);
+      cnt = wave_sum(cnt);
+      if (lane == 0) {
+        bc[0] = rho;
+        bc[1] = eta;
+        bc[2] = cnt;
+      }
     }
-    for (int j = lane + 64; j < nwg; j += 64) {
+  } else {
+    double m = INFINITY;
+    for (int j = threadIdx.x; j < nwg; j += NT)
+      if (b.part[j].nfin > 0) m = fmin(m, b.part[j].rho);
+    const double rho = block_min<NW>(m, lds);
+    double eta = 0.0, cnt = 0.0;
+    for (int j = threadIdx.x; j < nwg; j += NT) {
       const WgPartial q = b.part[j];
       const double sc = (q.nfin > 0) ? exp(-(q.rho - rho) / p.lam_d) : 0.0;
       b.scale[j] = sc;
@@ -261,9 +274,9 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
       eta += q.eta * sc;
       cnt += q.nfin;
     }
-    eta = wave_sum(eta);
-    cnt = wave_sum(cnt);
-    if (lane == 0) {
+    eta = block_sum<NW>(eta, lds);
+    cnt = block_sum<NW>(cnt, lds);
+    if (threadIdx.x == 0) {
       bc[0] = rho;
       bc[1] = eta;
       bc[2] = cnt;

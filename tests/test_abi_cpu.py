@@ -171,3 +171,13 @@ def test_admission_by_footprint():
     ok, refused, used = serving.admit(cfgs, cap)
     assert ok[:10] == list(range(10)) and used <= cap
     assert sorted(ok + refused) == list(range(64))
+
+
+def test_study_success_criterion():
+    from paper_1807_06108_amd import study
+    t = np.zeros((3, 10))
+    t[1, -1] = 0.3           # leaves the 0.25 rad band at the last step
+    t[2, :5] = 3.0           # down early, upright over the last 5 steps
+    t[0] = 2 * np.pi         # a full turn is upright again
+    assert list(study.swing_up_success(t, 5, 0.25)) == [True, False, True]
+    assert list(study.swing_up_success(t, 6, 0.25)) == [True, False, False]
