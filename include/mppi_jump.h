@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define MPPI_JUMP_ABI_VERSION 1
+#define MPPI_JUMP_ABI_VERSION 2
 
 #define MPPI_JUMP_MAX_N 12      /* state dimension bound            */
 #define MPPI_JUMP_MAX_M 4       /* control dimension bound          */
@@ -122,6 +122,11 @@ typedef struct mppi_jump_config {
   uint64_t seed;         /* Philox key                                         */
   uint64_t controller_id;/* < 2^24; part of the Philox counter                 */
   uint64_t start_iteration; /* iteration index of the first step, < 2^32      */
+  int32_t full_sigma;    /* 0: Sigma_D = diag(sigma^2); 1: Sigma_D = L L^T     */
+  float sigma_L[16];     /* full_sigma: Cholesky factor L of Sigma_D (Sec. IV-B
+                            eps_D ~ N(0, Sigma_D)), row-major 4 x 4 of which
+                            the leading m x m block is used: lower triangular,
+                            diagonal > 0; sigma[] is then ignored            */
 } mppi_jump_config;
 /* params: cartpole  = {m_cart, m_pole, half_length, g}
  *         quadrotor = {mass, Jx, Jy, Jz, arm, k_yaw, g, tilt_max, z_min}
@@ -299,9 +304,11 @@ int mppi_jump_pool_create(mppi_jump_ctx* const* ctxs, int32_t n, int32_t max_inf
 /* Enqueue a tick on `stream` through `slot`: for each request i < count,
  * controller ids[i] (distinct, in [0, n)) takes iters iterations from the
  * host state states[12 i .. 12 i + n_i) (fp32) and shifts.  With dist
- * (host, [count][4] fp32, disturbance added to the control channels) the
- * tick then steps each request's simulated plant once from its state under
- * u_0 + dist.  Host arrays are read during the call only.  Asynchronous. */
+ * (host, [count][8] fp32: words 0..3 added to the control channels, words
+ * 4..6 a world-frame body force applied by the quadrotor model, word 7
+ * unused) the tick then steps each request's simulated plant once from its
+ * state under u_0 + dist.  Host arrays are read during the call only.
+ * Asynchronous. */
 int mppi_jump_pool_tick(mppi_jump_pool* pool, const int32_t* ids, const float* states,
                         const float* dist, int32_t count, int32_t iters, int32_t slot,
                         void* stream);

@@ -19,7 +19,8 @@ Readings of passages the paper leaves open (listed again in the design notes):
   * eps is a per-step control-space perturbation, so the paper's
     eps/sqrt(dt) is eps here and the update is U += sum w eps;
   * IS terms per step, from the Gaussian likelihood ratio behind eq. (35)
-    with sampling covariance Sigma_s = diag(sigma^2):
+    with sampling covariance Sigma_s = diag(sigma^2), or Sigma_s = L L^T
+    for a full covariance given by its Cholesky factor L:
         lambda * c * U_t^T Sigma_s^-1 eps_t + 0.5 lambda (c - 1) eps_t^T Sigma_s^-1 eps_t
     (channels with sigma = 0 contribute nothing); the IS term uses the full
     perturbation including a control-channel jump, as Algorithm 1 adds the
@@ -59,7 +60,10 @@ def params(cfg):
     n, m, q = noise.DIMS[cfg["dynamics"]]
     sig = f32(cfg["sigma"][:m])
     iv = np.where(sig > 0, 1.0 / np.where(sig > 0, sig * sig, 1.0), 0.0)
-    return dict(
+    L = noise.cholesky_factor(cfg)
+    # inverse sampling covariance: L^-T L^-1 from the factor, or diagonal
+    Pinv = None if L is None else np.linalg.inv(L @ L.T)
+    return dict(Pinv=Pinv,
         n=n, m=m, q=q,
         dt=float(f32(cfg["dt"])), lam=float(f32(cfg["lambda"])),
         alpha=float(f32(cfg.get("alpha", 1.0))), c=float(f32(cfg.get("c", 1.0))),
@@ -95,8 +99,12 @@ def rollout(cfg, x0, U, eps, gust):
         qx = models.state_cost(x, p["Q"], p["goal"]) + p["pen"] * crashed
         if p["cost_form"] == 0:
             ctrl = 0.5 * float((p["R"] * U[t] * U[t]).sum())
-            is_cross = lam * c * (U[t][None, :] * e * p["inv_var"]).sum(axis=1)
-            is_var = 0.5 * lam * (c - 1.0) * (e * e * p["inv_var"]).sum(axis=1)
+            if p["Pinv"] is None:
+                is_cross = lam * c * (U[t][None, :] * e * p["inv_var"]).sum(axis=1)
+                is_var = 0.5 * lam * (c - 1.0) * (e * e * p["inv_var"]).sum(axis=1)
+            else:
+                is_cross = lam * c * (e @ (p["Pinv"] @ U[t]))
+                is_var = 0.5 * lam * (c - 1.0) * np.einsum("ki,ij,kj->k", e, p["Pinv"], e)
             S = S + (qx + ctrl) * dt + is_cross + is_var
         else:
             S = S + (qx + 0.5 * (p["R"] * v * v).sum(axis=1)) * dt

@@ -148,14 +148,28 @@ def sample(cfg, iteration, k_index=None):
     return z_D, N, z_J
 
 
+def cholesky_factor(cfg):
+    """The m x m Gaussian covariance factor L (Sigma_D = L L^T) of a
+    configuration with a full covariance, as fp64 of its fp32 entries, or
+    None for the diagonal form (Sigma_D = diag sigma^2)."""
+    if not int(cfg.get("full_sigma", 0)):
+        return None
+    m = DIMS[cfg["dynamics"]][1]
+    L = np.asarray(cfg["sigma_L"], dtype=np.float32).astype(np.float64).reshape(4, 4)
+    return L[:m, :m]
+
+
 def compose(cfg, z_D, N, z_J):
     """Control perturbation eps [K', T, m] and body-force disturbance
-    gust [K', T, 3] from the standard draws (readings in the module header)."""
+    gust [K', T, 3] from the standard draws (readings in the module header).
+    The Gaussian part is sigma * z_D, or L z_D for a full covariance
+    Sigma_D = L L^T (Sec. IV-B: eps_D ~ N(0, Sigma_D))."""
     dyn = cfg["dynamics"]
     n, m, q = DIMS[dyn]
     sigma = np.asarray(cfg["sigma"][:m], dtype=np.float32).astype(np.float64)
     sigJ = np.asarray(cfg["sigma_J"][:q], dtype=np.float32).astype(np.float64)
-    eps_D = z_D * sigma
+    L = cholesky_factor(cfg)
+    eps_D = z_D * sigma if L is None else z_D @ L.T
     J = np.sqrt(N.astype(np.float64))[..., None] * z_J * sigJ
     if JUMP_IN_CONTROL[dyn]:
         return eps_D + J, np.zeros(J.shape[:-1] + (3,))

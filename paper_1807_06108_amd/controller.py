@@ -246,11 +246,16 @@ class Pool:
 
     def tick(self, ids, states, dist=None, iters=1, slot=0, stream=None):
         """Enqueue one MPC step for controllers ids (int array [c]) from host
-        states [c, 12] (fp32); with dist [c, 4] also step each plant."""
+        states [c, 12] (fp32); with dist also step each plant: [c, 4]
+        control-channel disturbances, or [c, 8] with a world-frame body
+        force in columns 4..6 (quadrotor)."""
         ids = np.ascontiguousarray(ids, dtype=np.int32)
         states = np.ascontiguousarray(states, dtype=np.float32).reshape(len(ids), 12)
         if dist is not None:
-            dist = np.ascontiguousarray(dist, dtype=np.float32).reshape(len(ids), 4)
+            dist = np.asarray(dist, dtype=np.float32).reshape(len(ids), -1)
+            full = np.zeros((len(ids), 8), dtype=np.float32)
+            full[:, :dist.shape[1]] = dist
+            dist = full
         native.check(native.lib().mppi_jump_pool_tick(self.pl, _np_ptr(ids), _np_ptr(states),
                                                       _np_ptr(dist), len(ids), int(iters),
                                                       int(slot), _stream_handle(stream)))

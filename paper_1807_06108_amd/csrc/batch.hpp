@@ -77,7 +77,9 @@ namespace mppi {
 // Serving form: a tick advances a subset of a resident pool.  The request
 // record of a tick (device memory) holds, in longest-first order, the
 // controller ids [count], the tile prefix [count + 1], the states
-// [count][12] and the plant disturbances [count][4]; workgroup b finds its
+// [count][12] and the plant disturbances [count][kPoolDist] (words 0..3
+// added to the control channels, words 4..6 a world-frame body force for
+// the models that take one); workgroup b finds its
 // request by binary search over the prefix.  Request i writes u_0 to
 // out[16 i .. 16 i + m) and, when the plant runs, the next plant state to
 // out[16 i + 4 .. 16 i + 4 + n).
@@ -92,6 +94,7 @@ struct PoolTick {
 };
 
 constexpr int kPoolOut = 16;
+constexpr int kPoolDist = 8;
 
 __device__ __forceinline__ int find_request(const int* prefix, int count, int b) {
   int lo = 0, hi = count;  // prefix[lo] <= b < prefix[hi]
@@ -123,7 +126,7 @@ __device__ __forceinline__ void pool_plant_one(const DevParams& p, const float* 
                                                float* out) {
   using Md = Model<DYN>;
   float s[Md::N], v[Md::M];
-  const float gust[3] = {0.f, 0.f, 0.f};
+  const float gust[3] = {d[4], d[5], d[6]};
 #pragma unroll
   for (int j = 0; j < Md::N; ++j) s[j] = x[j];
 #pragma unroll
@@ -134,14 +137,15 @@ __device__ __forceinline__ void pool_plant_one(const DevParams& p, const float* 
 }
 
 // Simulated plant of each request: one explicit Euler step from the request
-// state under u_0 + disturbance (the same step as plant_kernel).
+// state under u_0 + disturbance and, for the quadrotor, the body force (the
+// step of plant_kernel with a gust input).
 __global__ __launch_bounds__(64) void pool_plant_kernel(const BatchDesc* __restrict__ descs,
                                                         const PoolTick tick) {
   const int i = blockIdx.x * 64 + threadIdx.x;
   if (i >= tick.count) return;
   const BatchDesc& d = descs[tick.ids[i]];
   const float* x = tick.states + 12 * i;
-  const float* w = tick.dist + 4 * i;
+  const float* w = tick.dist + kPoolDist * i;
   float* out = tick.out + kPoolOut * i;
   switch (d.dyn) {
     case MPPI_DYN_LINEAR: pool_plant_one<MPPI_DYN_LINEAR>(d.p, x, w, out); break;

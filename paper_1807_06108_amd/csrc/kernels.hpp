@@ -44,6 +44,12 @@ struct DevParams {
   float Q[12], Qf[12], goal[12];
   ModelConsts mc;
   uint32_t th[MPPI_JUMP_MAX_LEVELS];
+  // full Gaussian covariance (full = 1): Cholesky factor L, and Sigma^-1
+  // scaled by lambda c (Pc) and lambda (c - 1) / 2 (Pv), row-major 4 x 4;
+  // read from the kernel arguments (staging them in LDS with the other
+  // constants costs the light models ~45 vector registers)
+  int full;
+  float L[16], Pc[16], Pv[16];
 };
 
 struct Buffers {
@@ -400,7 +406,9 @@ struct Noise {
   int n;
 };
 
-template <int DYN, bool JUMPS>
+// FULL: the Gaussian part is L z for a full covariance L L^T (multi-channel
+// models only; the factor is read from the kernel arguments).
+template <int DYN, bool JUMPS, bool FULL = false>
 __device__ __forceinline__ void draw_noise(Noise<DYN, JUMPS>& o, const DevParams& p,
                                            const Consts& cs, uint32_t t, uint32_t k, uint32_t it) {
   using Md = Model<DYN>;
@@ -421,8 +429,20 @@ __device__ __forceinline__ void draw_noise(Noise<DYN, JUMPS>& o, const DevParams
     else
       o.z[i] = box_muller_cos(w[i], w[i + 1]);
   }
+  // (one-channel models: the host passes a full covariance as sigma = L00)
+  if constexpr (FULL) {
+    // eps_D = L z (lower-triangular factor of the covariance)
 #pragma unroll
-  for (int j = 0; j < Md::M; ++j) o.eps[j] = cs.sigma[j] * o.z[j];
+    for (int j = 0; j < Md::M; ++j) {
+      float e = 0.f;
+#pragma unroll
+      for (int k = 0; k <= j; ++k) e += p.L[4 * j + k] * o.z[k];
+      o.eps[j] = e;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < Md::M; ++j) o.eps[j] = cs.sigma[j] * o.z[j];
+  }
   o.gust[0] = o.gust[1] = o.gust[2] = 0.f;
   o.n = 0;
   if constexpr (JUMPS) {
@@ -448,15 +468,27 @@ __device__ __forceinline__ void kahan_add(float& s, float& comp, float term) {
 // State-free part of the stage cost of eqs. (34)-(35): nominal control cost
 // times dt plus the importance-sampling terms (IT form), or the control cost
 // of the applied control times dt (SO form).
-template <int M, int FORM>
+template <int M, int FORM, bool FULL = false>
 __device__ __forceinline__ float state_free_cost(const DevParams& p, const Consts& cs,
                                                  const float* u, const float* eps) {
   if constexpr (FORM == MPPI_COST_IT) {
     float ctrl = 0.f, is = 0.f;
+    if constexpr (FULL) {
+      // lambda c u^T Sigma^-1 eps + lambda (c - 1) / 2 eps^T Sigma^-1 eps
 #pragma unroll
-    for (int j = 0; j < M; ++j) {
-      ctrl += cs.halfR[j] * u[j] * u[j];
-      is += (cs.isc[j] * u[j] + cs.isv[j] * eps[j]) * eps[j];
+      for (int j = 0; j < M; ++j) {
+        ctrl += cs.halfR[j] * u[j] * u[j];
+        float a = 0.f;
+#pragma unroll
+        for (int k = 0; k < M; ++k) a += p.Pc[4 * j + k] * u[k] + p.Pv[4 * j + k] * eps[k];
+        is += a * eps[j];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        ctrl += cs.halfR[j] * u[j] * u[j];
+        is += (cs.isc[j] * u[j] + cs.isv[j] * eps[j]) * eps[j];
+      }
     }
     return ctrl * p.dt + is;
   } else {
@@ -474,7 +506,7 @@ __device__ __forceinline__ float state_free_cost(const DevParams& p, const Const
 // update (one kernel per iteration); otherwise it only forms the statistics
 // and update_kernel follows.
 // One workgroup (tile wg of nwg) of the one-sample-per-lane rollout.
-template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED>
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL = false>
 __device__ __forceinline__ void rollout_lane_tile(const DevParams& p, const Buffers& b,
                                                   const float* __restrict__ x0,
                                                   const float* __restrict__ U, int R,
@@ -496,10 +528,10 @@ __device__ __forceinline__ void rollout_lane_tile(const DevParams& p, const Buff
   // software pipeline: the draws of step t + 1 are formed while step t's
   // dynamics run (they do not depend on the state)
   Noise<DYN, JUMPS> nxt;
-  draw_noise(nxt, p, cs, 0u, (uint32_t)k, it);
+  draw_noise<DYN, JUMPS, FULL>(nxt, p, cs, 0u, (uint32_t)k, it);
   for (int t = 0; t < p.T; ++t) {
     const Noise<DYN, JUMPS> cur = nxt;
-    draw_noise(nxt, p, cs, (uint32_t)(t + 1), (uint32_t)k, it);
+    draw_noise<DYN, JUMPS, FULL>(nxt, p, cs, (uint32_t)(t + 1), (uint32_t)k, it);
 
     // modified path cost, eqs. (34)-(35), on the pre-step state
     float u[M];
@@ -512,7 +544,7 @@ __device__ __forceinline__ void rollout_lane_tile(const DevParams& p, const Buff
       qx += cs.Q[i] * d * d;
     }
     if constexpr (Md::CAN_CRASH) qx += crashed ? p.pen : 0.f;
-    const float term = qx * p.dt + state_free_cost<M, FORM>(p, cs, u, cur.eps);
+    const float term = qx * p.dt + state_free_cost<M, FORM, FULL>(p, cs, u, cur.eps);
     kahan_add(S, comp, term);
 
     float v[M];
@@ -558,12 +590,13 @@ __device__ __forceinline__ void rollout_lane_tile(const DevParams& p, const Buff
   rollout_epilogue<kBlock, FUSED>(p, b, Sd, active, R, sh, wg, nwg);
 }
 
-template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED>
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL>
 __global__ __launch_bounds__(256) void rollout_kernel(const DevParams p, const Buffers b,
                                                       const float* __restrict__ x0,
                                                       const float* __restrict__ U, int R,
                                                       const ShiftArgs sh) {
-  rollout_lane_tile<DYN, JUMPS, DEBUG, FORM, FUSED>(p, b, x0, U, R, sh, blockIdx.x, gridDim.x);
+  rollout_lane_tile<DYN, JUMPS, DEBUG, FORM, FUSED, FULL>(p, b, x0, U, R, sh, blockIdx.x,
+                                                         gridDim.x);
 }
 
 // Statistics of caller-provided costs (mppi_jump_set of S), with the

@@ -113,9 +113,20 @@ int validate(const mppi_jump_config* c, int& n, int& m, int& q, std::vector<uint
   if (c->debug_dump != 0 && c->debug_dump != 1) return fail(MPPI_EINVAL, "debug_dump must be 0 or 1");
   if (c->schedule < MPPI_SCHED_AUTO || c->schedule > MPPI_SCHED_WAVE_SPECIALISED)
     return fail(MPPI_EINVAL, "unknown schedule %d", c->schedule);
-  for (int j = 0; j < m; ++j)
-    if (!(std::isfinite(c->sigma[j]) && c->sigma[j] >= 0.f))
-      return fail(MPPI_EINVAL, "sigma[%d] must be finite and >= 0", j);
+  if (c->full_sigma != 0 && c->full_sigma != 1) return fail(MPPI_EINVAL, "full_sigma must be 0 or 1");
+  if (c->full_sigma) {
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        const float v = c->sigma_L[4 * i + j];
+        if (!std::isfinite(v)) return fail(MPPI_EINVAL, "sigma_L[%d][%d] must be finite", i, j);
+        if (j > i && v != 0.f) return fail(MPPI_EINVAL, "sigma_L must be lower triangular");
+        if (j == i && !(v > 0.f)) return fail(MPPI_EINVAL, "sigma_L[%d][%d] must be > 0", i, i);
+      }
+  } else {
+    for (int j = 0; j < m; ++j)
+      if (!(std::isfinite(c->sigma[j]) && c->sigma[j] >= 0.f))
+        return fail(MPPI_EINVAL, "sigma[%d] must be finite and >= 0", j);
+  }
   for (int i = 0; i < q; ++i)
     if (!(std::isfinite(c->sigma_J[i]) && c->sigma_J[i] >= 0.f))
       return fail(MPPI_EINVAL, "sigma_J[%d] must be finite and >= 0", i);
@@ -213,9 +224,35 @@ DevParams make_params(const mppi_jump_config* c, int n, int m, int q, const Layo
   p.alpha = c->alpha;
   p.pen = c->crash_penalty;
   const double lam = c->lambda, cc = c->c;
+  // a one-channel covariance L L^T is the diagonal form with sigma = L00
+  float sig_in[4] = {c->sigma[0], c->sigma[1], c->sigma[2], c->sigma[3]};
+  if (c->full_sigma && m == 1) sig_in[0] = c->sigma_L[0];
+  if (c->full_sigma && m > 1) {
+    // Sigma_D = L L^T: eps_D = L z, and the IS terms take Sigma_D^-1 =
+    // L^-T L^-1 (forward substitution in fp64), pre-scaled by lambda c and
+    // lambda (c - 1) / 2
+    double Li[4][4] = {};
+    for (int i = 0; i < m; ++i) {
+      Li[i][i] = 1.0 / (double)c->sigma_L[4 * i + i];
+      for (int j = 0; j < i; ++j) {
+        double acc = 0.0;
+        for (int k = j; k < i; ++k) acc += (double)c->sigma_L[4 * i + k] * Li[k][j];
+        Li[i][j] = -acc / (double)c->sigma_L[4 * i + i];
+      }
+    }
+    p.full = 1;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j) {
+        double P = 0.0;
+        for (int k = 0; k < m; ++k) P += Li[k][i] * Li[k][j];
+        p.L[4 * i + j] = c->sigma_L[4 * i + j];
+        p.Pc[4 * i + j] = (float)(lam * cc * P);
+        p.Pv[4 * i + j] = (float)(0.5 * lam * (cc - 1.0) * P);
+      }
+  }
   for (int j = 0; j < m; ++j) {
-    p.sigma[j] = c->sigma[j];
-    const double s2 = (double)c->sigma[j] * (double)c->sigma[j];
+    p.sigma[j] = sig_in[j];
+    const double s2 = (double)sig_in[j] * (double)sig_in[j];
     p.isc[j] = s2 > 0 ? (float)(lam * cc / s2) : 0.f;
     p.isv[j] = s2 > 0 ? (float)(0.5 * lam * (cc - 1.0) / s2) : 0.f;
     p.halfR[j] = 0.5f * c->R[j];
@@ -277,41 +314,52 @@ struct mppi_jump_ctx {
 
 namespace {
 
-template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED>
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL>
 int launch_rollout_t(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, const ShiftArgs& sh) {
   if (ctx->L.ws) {
-    rollout_ws_kernel<DYN, JUMPS, DEBUG, FORM, FUSED><<<dim3(ctx->L.nwg), dim3(64 * WsWaves<DYN>::W),
-                                                       ws_ring_bytes<DYN>(), s>>>(
-        ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R, sh);
+    rollout_ws_kernel<DYN, JUMPS, DEBUG, FORM, FUSED, FULL>
+        <<<dim3(ctx->L.nwg), dim3(64 * WsWaves<DYN>::W), ws_ring_bytes<DYN>(), s>>>(
+            ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R, sh);
     LAUNCH_CHECK("rollout_ws_kernel");
   } else {
-    rollout_kernel<DYN, JUMPS, DEBUG, FORM, FUSED>
+    rollout_kernel<DYN, JUMPS, DEBUG, FORM, FUSED, FULL>
         <<<dim3(ctx->L.nwg), dim3(kBlock), 0, s>>>(ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R, sh);
     LAUNCH_CHECK("rollout_kernel");
   }
   return MPPI_OK;
 }
 
-template <int DYN, bool JUMPS, bool DEBUG>
+template <int DYN, bool JUMPS, bool DEBUG, bool FULL>
 int launch_rollout_form(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, bool fused,
                         const ShiftArgs& sh) {
   const bool it = ctx->cfg.cost_form == MPPI_COST_IT;
   if (fused)
-    return it ? launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_IT, true>(ctx, x0, s, sh)
-              : launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_SO, true>(ctx, x0, s, sh);
-  return it ? launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_IT, false>(ctx, x0, s, sh)
-            : launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_SO, false>(ctx, x0, s, sh);
+    return it ? launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_IT, true, FULL>(ctx, x0, s, sh)
+              : launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_SO, true, FULL>(ctx, x0, s, sh);
+  return it ? launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_IT, false, FULL>(ctx, x0, s, sh)
+            : launch_rollout_t<DYN, JUMPS, DEBUG, MPPI_COST_SO, false, FULL>(ctx, x0, s, sh);
 }
 
+template <int DYN, bool FULL>
+int launch_rollout_full(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, bool fused,
+                        const ShiftArgs& sh) {
+  const bool jumps = ctx->p.n_th > 0, dbg = ctx->cfg.debug_dump != 0;
+  if (jumps)
+    return dbg ? launch_rollout_form<DYN, true, true, FULL>(ctx, x0, s, fused, sh)
+               : launch_rollout_form<DYN, true, false, FULL>(ctx, x0, s, fused, sh);
+  return dbg ? launch_rollout_form<DYN, false, true, FULL>(ctx, x0, s, fused, sh)
+             : launch_rollout_form<DYN, false, false, FULL>(ctx, x0, s, fused, sh);
+}
+
+// The full-covariance variants exist for the multi-channel model only (a
+// one-channel covariance is passed as its diagonal form).
 template <int DYN>
 int launch_rollout_dyn(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, bool fused,
                        const ShiftArgs& sh) {
-  const bool jumps = ctx->p.n_th > 0, dbg = ctx->cfg.debug_dump != 0;
-  if (jumps)
-    return dbg ? launch_rollout_form<DYN, true, true>(ctx, x0, s, fused, sh)
-               : launch_rollout_form<DYN, true, false>(ctx, x0, s, fused, sh);
-  return dbg ? launch_rollout_form<DYN, false, true>(ctx, x0, s, fused, sh)
-             : launch_rollout_form<DYN, false, false>(ctx, x0, s, fused, sh);
+  if constexpr (Model<DYN>::M > 1) {
+    if (ctx->p.full) return launch_rollout_full<DYN, true>(ctx, x0, s, fused, sh);
+  }
+  return launch_rollout_full<DYN, false>(ctx, x0, s, fused, sh);
 }
 
 // Timing brackets: an event pair around a span of back-to-back rollout
@@ -662,6 +710,7 @@ int batch_check(mppi_jump_ctx* const* ctxs, int32_t n, BatchLayout& BL, bool& ws
       return fail(MPPI_EUNSUPPORTED, "context %d: K=%d needs more than %d rollout workgroups", i,
                   c->cfg.K, kFusedMaxWg);
     if (c->cfg.debug_dump) return fail(MPPI_EUNSUPPORTED, "context %d has debug_dump set", i);
+    if (c->p.full) return fail(MPPI_EUNSUPPORTED, "context %d has a full noise covariance", i);
     if (i == 0) ws = c->L.ws;
     if (c->L.ws != ws) return fail(MPPI_EINVAL, "contexts of one batch must share a rollout schedule");
     ntiles += c->L.nwg;
@@ -817,7 +866,7 @@ int mppi_jump_batch_destroy(mppi_jump_batch* bt) {
 namespace {
 
 // Request record of one slot: ids [n], prefix [n + 1], states [n][12],
-// disturbances [n][4], outputs [n][16] (4-byte words; parts 256-byte aligned).
+// disturbances [n][8], outputs [n][16] (4-byte words; parts 256-byte aligned).
 struct SlotLayout {
   size_t ids, prefix, states, dist, out, total;
 };
@@ -833,7 +882,7 @@ SlotLayout slot_layout(int n) {
   S.ids = take((size_t)n * 4);
   S.prefix = take((size_t)(n + 1) * 4);
   S.states = take((size_t)n * 12 * 4);
-  S.dist = take((size_t)n * 4 * 4);
+  S.dist = take((size_t)n * kPoolDist * 4);
   S.out = take((size_t)n * kPoolOut * 4);
   S.total = off;
   return S;
@@ -1008,7 +1057,7 @@ int mppi_jump_pool_tick(mppi_jump_pool* pl, const int32_t* ids, const float* sta
       h_pre[j] = tiles;
       tiles += c->L.nwg;
       std::memcpy(h_st + 12 * j, states + 12 * i, sizeof(float) * c->n);
-      if (dist) std::memcpy(h_di + 4 * j, dist + 4 * i, sizeof(float) * c->m);
+      if (dist) std::memcpy(h_di + kPoolDist * j, dist + kPoolDist * i, sizeof(float) * kPoolDist);
     }
     h_pre[count] = tiles;
     const hipStream_t s = static_cast<hipStream_t>(stream);

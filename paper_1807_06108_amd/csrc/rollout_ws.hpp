@@ -36,7 +36,7 @@ constexpr size_t ws_ring_bytes() {
   return sizeof(float) * 2 * kWsChunk * WsRing<DYN>::NF * 64;
 }
 
-template <int DYN, bool JUMPS, bool DEBUG, int FORM>
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FULL>
 __device__ __forceinline__ void ws_produce(const DevParams& p, const Consts& cs, const Buffers& b,
                                            const float* __restrict__ U, float* slot, int t,
                                            int k, bool active, uint32_t it) {
@@ -44,7 +44,7 @@ __device__ __forceinline__ void ws_produce(const DevParams& p, const Consts& cs,
   using Rg = WsRing<DYN>;
   constexpr int M = Md::M, Q = Md::Q;
   Noise<DYN, JUMPS> nz;
-  draw_noise(nz, p, cs, (uint32_t)t, (uint32_t)k, it);
+  draw_noise<DYN, JUMPS, FULL>(nz, p, cs, (uint32_t)t, (uint32_t)k, it);
   float u[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) u[j] = U[t * M + j];
@@ -53,7 +53,7 @@ __device__ __forceinline__ void ws_produce(const DevParams& p, const Consts& cs,
   for (int j = 0; j < M; ++j) slot[j * 64 + lane] = u[j] + nz.eps[j];
 #pragma unroll
   for (int i = 0; i < Rg::NG; ++i) slot[(M + i) * 64 + lane] = nz.gust[i];
-  slot[(Rg::NF - 1) * 64 + lane] = state_free_cost<M, FORM>(p, cs, u, nz.eps);
+  slot[(Rg::NF - 1) * 64 + lane] = state_free_cost<M, FORM, FULL>(p, cs, u, nz.eps);
 #pragma unroll
   for (int j = 0; j < M; ++j) b.eps[(size_t)(t * M + j) * p.Ks + k] = nz.eps[j];
   if constexpr (DEBUG) {
@@ -75,21 +75,15 @@ struct WsState {
   bool crashed;
 };
 
-// One step of the state recursion from a ring slot: running cost on the
-// pre-step state, then the explicit Euler step (frozen once crashed).
+// One step of the state recursion: running cost on the pre-step state, then
+// the explicit Euler step (frozen once crashed).  v: applied controls, gust:
+// body-force disturbance (zero for jumps through the control channel), pre:
+// the state-free part of the stage cost.
 template <int DYN>
-__device__ __forceinline__ void ws_consume(const DevParams& p, const Consts& cs, WsState<DYN>& st,
-                                           const float* slot) {
+__device__ __forceinline__ void ws_step(const DevParams& p, const Consts& cs, WsState<DYN>& st,
+                                        const float* v, const float* gust, float pre) {
   using Md = Model<DYN>;
-  using Rg = WsRing<DYN>;
-  constexpr int N = Md::N, M = Md::M;
-  const int lane = threadIdx.x & 63;
-  float v[M], gust[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-  for (int j = 0; j < M; ++j) v[j] = slot[j * 64 + lane];
-#pragma unroll
-  for (int i = 0; i < Rg::NG; ++i) gust[i] = slot[(M + i) * 64 + lane];
-  const float pre = slot[(Rg::NF - 1) * 64 + lane];
+  constexpr int N = Md::N;
   float qx = 0.f;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
@@ -111,8 +105,23 @@ __device__ __forceinline__ void ws_consume(const DevParams& p, const Consts& cs,
   }
 }
 
+// The step of a ring slot, read from LDS.
+template <int DYN>
+__device__ __forceinline__ void ws_consume(const DevParams& p, const Consts& cs, WsState<DYN>& st,
+                                           const float* slot) {
+  using Rg = WsRing<DYN>;
+  constexpr int M = Model<DYN>::M;
+  const int lane = threadIdx.x & 63;
+  float v[M], gust[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int j = 0; j < M; ++j) v[j] = slot[j * 64 + lane];
+#pragma unroll
+  for (int i = 0; i < Rg::NG; ++i) gust[i] = slot[(M + i) * 64 + lane];
+  ws_step<DYN>(p, cs, st, v, gust, slot[(Rg::NF - 1) * 64 + lane]);
+}
+
 // One workgroup (tile wg of nwg) of the wave-specialised rollout, W waves.
-template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, int W>
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, int W, bool FULL = false>
 __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffers& b,
                                                 const float* __restrict__ x0,
                                                 const float* __restrict__ U, int R,
@@ -148,7 +157,8 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
         float(*buf)[SLOT] = ring[c & 1];
         for (int s = wave - 1; s < kWsChunk; s += NP) {
           const int t = c * kWsChunk + s;
-          if (t < T) ws_produce<DYN, JUMPS, DEBUG, FORM>(p, cs, b, U, buf[s], t, k, active, it);
+          if (t < T)
+            ws_produce<DYN, JUMPS, DEBUG, FORM, FULL>(p, cs, b, U, buf[s], t, k, active, it);
         }
       }
     } else if (c > 0) {
@@ -180,13 +190,13 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
   rollout_epilogue<kWsSamples, FUSED, 64 * W>(p, b, Sd, wave == 0 && active, R, sh, wg, nwg);
 }
 
-template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED>
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL>
 __global__ __launch_bounds__(64 * WsWaves<DYN>::W) void rollout_ws_kernel(const DevParams p,
                                                                          const Buffers b,
                                                                          const float* __restrict__ x0,
                                                                          const float* __restrict__ U,
                                                                          int R, const ShiftArgs sh) {
-  rollout_ws_tile<DYN, JUMPS, DEBUG, FORM, FUSED, WsWaves<DYN>::W>(p, b, x0, U, R, sh, blockIdx.x,
+  rollout_ws_tile<DYN, JUMPS, DEBUG, FORM, FUSED, WsWaves<DYN>::W, FULL>(p, b, x0, U, R, sh, blockIdx.x,
                                                                    gridDim.x);
 }
 

@@ -55,6 +55,7 @@ class Config(ctypes.Structure):
         ("crash_penalty", ctypes.c_float), ("schedule", ctypes.c_int32),
         ("seed", ctypes.c_uint64), ("controller_id", ctypes.c_uint64),
         ("start_iteration", ctypes.c_uint64),
+        ("full_sigma", ctypes.c_int32), ("sigma_L", ctypes.c_float * 16),
     ]
 
 

@@ -45,7 +45,20 @@ def base_config(dynamics):
                 debug_dump=0, sigma=[0.0] * 4, sigma_J=[0.0] * 4,
                 u_init=[0.0] * 4, R=[0.0] * 4, Q=[0.0] * 12, Qf=[0.0] * 12,
                 x_goal=[0.0] * 12, params=[0.0] * 12, crash_penalty=0.0, schedule=0,
-                seed=DEFAULT_SEED, controller_id=0, start_iteration=0)
+                seed=DEFAULT_SEED, controller_id=0, start_iteration=0,
+                full_sigma=0, sigma_L=[0.0] * 16)
+
+
+def random_cholesky(m, scale, seed):
+    """A seeded lower-triangular factor L (positive diagonal) of a full
+    Gaussian covariance L L^T of the m control channels, as the 16 row-major
+    entries of a 4 x 4 block."""
+    g = np.random.default_rng(seed)
+    L = np.tril(g.uniform(-0.5, 0.5, size=(m, m))) * scale
+    L[np.diag_indices(m)] = scale * g.uniform(0.6, 1.4, size=m)
+    out = np.zeros((4, 4))
+    out[:m, :m] = L
+    return [float(v) for v in out.reshape(-1)]
 
 
 def cartpole(**over):

@@ -181,3 +181,37 @@ def test_study_success_criterion():
     t[0] = 2 * np.pi         # a full turn is upright again
     assert list(study.swing_up_success(t, 5, 0.25)) == [True, False, True]
     assert list(study.swing_up_success(t, 6, 0.25)) == [True, False, False]
+
+
+def test_study_quadrotor_disturbances_and_success():
+    from paper_1807_06108_amd import study
+    d = study.quadrotor_disturbances(20000, 0.01, 0.5, 2.0, 100.0, seed=3)
+    assert d.shape == (20000, 8) and not d[:, 7].any()
+    assert abs(d[:, :4].std() - 0.5) < 0.02
+    # gust variance nu dt sigma_J^2 per axis
+    assert abs(d[:, 4:7].var() / (0.02 * 100.0 ** 2) - 1.0) < 0.15
+    params = workloads.QUAD_PARAMS
+    goal = [1.0, -1.0, 2.0]
+    t = np.zeros((3, 4, 12), dtype=np.float32)
+    t[:, :, 2] = 1.0
+    t[:, -1, :3] = goal
+    t[1, 2, 2] = -0.1            # below the ground once
+    t[2, -1, 0] = 1.6            # 0.6 m short of the target at the end
+    assert list(study.quadrotor_success(t, goal, params)) == [True, False, False]
+
+
+def test_full_covariance_validation():
+    good = workloads.quadrotor(full_sigma=1, sigma_L=workloads.random_cholesky(4, 0.5, seed=1))
+    assert native.workspace_bytes(good) > 0
+    upper = list(good["sigma_L"])
+    upper[1] = 0.1                     # above the diagonal
+    zero_diag = list(good["sigma_L"])
+    zero_diag[5] = 0.0
+    for bad in (dict(good, sigma_L=upper), dict(good, sigma_L=zero_diag),
+                dict(good, full_sigma=2)):
+        with pytest.raises(native.MppiError) as e:
+            native.workspace_bytes(bad)
+        assert e.value.code == native.C["MPPI_EINVAL"]
+    # a one-channel model: only L00 is read
+    cp = workloads.cartpole(full_sigma=1, sigma_L=[1.5] + [0.0] * 15, sigma=[0.0] * 4)
+    assert native.workspace_bytes(cp) > 0

@@ -287,3 +287,54 @@ def test_control_step_runs_iterations_then_shift():
     for i in range(3):
         U3 = mppi.iteration(cfg, x0, U3, i)["U"]
     assert np.array_equal(u0, U3[0]) and np.array_equal(Us[:-1], U3[1:])
+
+
+@pytest.mark.parametrize("c", [1.0, 0.5, 2.0])
+def test_full_covariance_is_terms_are_gaussian_likelihood_ratio(c):
+    # Full Sigma = L L^T on the quadrotor's four channels, state costs off:
+    # the IS terms plus 0.5 lambda c u^T Sigma^-1 u equal
+    # -lambda log[N(u + eps; 0, Sigma/c) / N(eps; 0, Sigma)] up to a constant.
+    L16 = workloads.random_cholesky(4, 0.8, seed=5)
+    cfg = workloads.quadrotor(K=40, T=1, c=c, full_sigma=1, sigma_L=L16, Q=[0.0] * 12,
+                              Qf=[0.0] * 12, R=[0.0] * 4, crash_penalty=0.0, nu=0.0)
+    p = mppi.params(cfg)
+    L = noise.cholesky_factor(cfg)
+    Sig = L @ L.T
+    lam = p["lam"]
+    rng = np.random.default_rng(2)
+    x0 = workloads.x0_for(cfg)
+    vals = []
+    for _ in range(4):
+        u = rng.uniform(-2, 2, size=4)
+        eps = rng.standard_normal((40, 1, 4)) @ L.T
+        S, _ = mppi.rollout(cfg, x0, u[None, :], eps, np.zeros((40, 1, 3)))
+        S = S + 0.5 * lam * p["c"] * u @ np.linalg.solve(Sig, u)
+        lr = -lam * (stats.multivariate_normal.logpdf(u + eps[:, 0, :], cov=Sig / p["c"])
+                     - stats.multivariate_normal.logpdf(eps[:, 0, :], cov=Sig))
+        vals.append(S - lr)
+    vals = np.concatenate(vals)
+    assert np.ptp(vals) < 1e-9 * max(1.0, np.abs(vals).max())
+
+
+def test_full_covariance_with_diagonal_factor_is_the_diagonal_form():
+    sig = [0.5, 0.3, 0.7, 0.4]
+    L16 = [0.0] * 16
+    for j in range(4):
+        L16[5 * j] = sig[j]
+    a = workloads.quadrotor(K=64, T=12, sigma=sig, c=0.7)
+    b = dict(a, full_sigma=1, sigma_L=L16)
+    x0 = workloads.x0_for(a)
+    U = workloads.U0_for(a, "random", seed=4).astype(np.float64)
+    ra, rb = mppi.iteration(a, x0, U, 0), mppi.iteration(b, x0, U, 0)
+    assert np.allclose(ra["eps"], rb["eps"], rtol=0, atol=1e-15)
+    assert np.allclose(ra["S"], rb["S"], rtol=1e-13, atol=1e-9)
+    assert np.allclose(ra["U"], rb["U"], rtol=0, atol=1e-12)
+
+
+def test_full_covariance_sample_covariance():
+    L16 = workloads.random_cholesky(4, 1.0, seed=9)
+    cfg = workloads.quadrotor(K=4096, T=16, full_sigma=1, sigma_L=L16, nu=0.0)
+    eps, _ = noise.compose(cfg, *noise.sample(cfg, 0))
+    e = eps.reshape(-1, 4)
+    L = noise.cholesky_factor(cfg)
+    assert np.abs(np.cov(e.T) - L @ L.T).max() < 0.05
