@@ -64,7 +64,19 @@ class Controller:
             pass
 
     def _s(self):
+        """The controller's stream, ordered after the work already queued on
+        torch's current stream (the inputs of the call)."""
+        cur = torch.cuda.current_stream()
+        if self.stream is not None and self.stream != cur:
+            self.stream.wait_stream(cur)
         return _stream_handle(self.stream)
+
+    def _publish(self):
+        """Order torch's current stream after the controller's stream, so
+        that results read on the current stream are complete."""
+        cur = torch.cuda.current_stream()
+        if self.stream is not None and self.stream != cur:
+            cur.wait_stream(self.stream)
 
     def _state(self, x0):
         x = torch.as_tensor(x0, dtype=torch.float32, device=self.device).contiguous()
@@ -87,6 +99,7 @@ class Controller:
             u0_out = torch.empty(self.m, dtype=torch.float32, device=self.device)
         native.check(native.lib().mppi_jump_control_step(self.ctx, _ptr(x), int(iters),
                                                          _ptr(u0_out), self._s()))
+        self._publish()
         return u0_out
 
     def rollout(self, x0):
@@ -103,16 +116,19 @@ class Controller:
         if out is None:
             out = torch.empty(self.m, dtype=torch.float32, device=self.device)
         native.check(native.lib().mppi_jump_shift(self.ctx, _ptr(out), self._s()))
+        self._publish()
         return out
 
     def plant_step(self, x, u, d):
         """Simulated plant: x <- Euler(x, u + d) on device tensors."""
         native.check(native.lib().mppi_jump_plant_step(self.ctx, _ptr(x), _ptr(u), _ptr(d), self._s()))
+        self._publish()
 
     # ------------------------------------------------------------- items
     def _get(self, item, nbytes, dtype, shape):
         out = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         native.check(native.lib().mppi_jump_get(self.ctx, native.ITEM[item], _ptr(out), nbytes, self._s()))
+        self._publish()
         return out.view(dtype).reshape(shape)
 
     @property

@@ -60,7 +60,7 @@ struct Buffers {
   WgPartial* part;    // [ceil(K/256)]
   double* scale;      // [ceil(K/256)] exp(-(rho_wg - rho)/lambda)
   double* upart;      // [T*m][nch]   chunk partials of update_kernel
-  double* wpart;      // [T*m][nwg]   workgroup partials of the fused epilogue
+  double* wpart;      // [nwg][T*m]   workgroup partials of the fused epilogue
   mppi_jump_stats* stats;
   uint32_t* counters; // [0] rollout, [1] update
   float* dbg_zD;      // [K][T][m]
@@ -199,7 +199,7 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
       }
       __syncthreads();
       if (wave == 0)
-        for (int i = lane; i < nrow; i += 64) b.wpart[(size_t)(base + i) * nwg + wg] = stage[i];
+        for (int i = lane; i < nrow; i += 64) b.wpart[(size_t)wg * R + base + i] = stage[i];
       __syncthreads();
     }
   }
@@ -218,6 +218,10 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
   __syncthreads();
   if (!is_last) return;
   __threadfence();
+  const WgPartial* parts = b.part;
+  const double* rows = b.wpart;  // row r of partial j at rows[j R + r]
+  const int n = nwg;
+
   // First pass of the fused update (rows [0, Rp)): when there are threads
   // to spare, each row's partials are split into S contiguous segments, one
   // thread each.  The segment's first kPre partials and the row's U are
@@ -228,27 +232,27 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
   float uold = 0.f;
   if constexpr (FUSED) {
     Rp = min(NT, R);
-    S = max(1, min(NT / Rp, (nwg + kPre - 1) / kPre));
-    L = (nwg + S - 1) / S;
+    S = max(1, min(NT / Rp, (n + kPre - 1) / kPre));
+    L = (n + S - 1) / S;
     seg = threadIdx.x / Rp;
     rr = threadIdx.x - seg * Rp;
     j0 = seg < S ? seg * L : 0;
-    j1 = seg < S ? min(nwg, j0 + L) : 0;
-    const double* wr = b.wpart + (size_t)rr * nwg;
+    j1 = seg < S ? min(n, j0 + L) : 0;
+    const double* wr = rows + rr;
 #pragma unroll
-    for (int q = 0; q < kPre; ++q) wpre[q] = j0 + q < j1 ? wr[j0 + q] : 0.0;
+    for (int q = 0; q < kPre; ++q) wpre[q] = j0 + q < j1 ? wr[(size_t)(j0 + q) * R] : 0.0;
     if (seg == 0) uold = b.U[rr];
   }
-  // combination: rho = min of the workgroup minima, the rescales
-  // exp(-(rho_wg - rho)/lambda), eta and the finite count.  Up to 64
+  // combination: rho = min of the partial minima, the rescales
+  // exp(-(rho_j - rho)/lambda), eta and the finite count.  Up to 64
   // partials: wavefront 0 alone, one per lane held in registers; more: the
   // whole workgroup with block reductions.
-  if (nwg <= 64) {
+  if (n <= 64) {
     if (wave == 0) {
-      const bool h = lane < nwg;
-      const double hrho = h ? b.part[lane].rho : INFINITY;
-      const double heta = h ? b.part[lane].eta : 0.0;
-      const int hfin = h ? b.part[lane].nfin : 0;
+      const bool h = lane < n;
+      const double hrho = h ? parts[lane].rho : INFINITY;
+      const double heta = h ? parts[lane].eta : 0.0;
+      const int hfin = h ? parts[lane].nfin : 0;
       const double rho = wave_min(hfin > 0 ? hrho : INFINITY);
       double eta = 0.0, cnt = 0.0;
       if (h) {
@@ -268,12 +272,12 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
     }
   } else {
     double m = INFINITY;
-    for (int j = threadIdx.x; j < nwg; j += NT)
-      if (b.part[j].nfin > 0) m = fmin(m, b.part[j].rho);
+    for (int j = threadIdx.x; j < n; j += NT)
+      if (parts[j].nfin > 0) m = fmin(m, parts[j].rho);
     const double rho = block_min<NW>(m, lds);
     double eta = 0.0, cnt = 0.0;
-    for (int j = threadIdx.x; j < nwg; j += NT) {
-      const WgPartial q = b.part[j];
+    for (int j = threadIdx.x; j < n; j += NT) {
+      const WgPartial q = parts[j];
       const double sc = (q.nfin > 0) ? exp(-(q.rho - rho) / p.lam_d) : 0.0;
       b.scale[j] = sc;
       if constexpr (FUSED) sc_lds[j] = sc;
@@ -292,7 +296,7 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
   const double rho = bc[0], eta = bc[1], cnt = bc[2];
   const bool ok = cnt > 0;
   if constexpr (FUSED) {
-    // U[r] += alpha / eta * sum_wg scale_wg P[r][wg]: each segment is summed
+    // U[r] += alpha / eta * sum_j scale_j P[r][j]: each segment is summed
     // with four accumulators in a fixed pattern, the segment sums in segment
     // order
     if (ok) {
@@ -301,16 +305,16 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
         const bool first = base == 0;
         if (!first) {
           Rp = min(NT, R - base);
-          S = max(1, min(NT / Rp, (nwg + kPre - 1) / kPre));
-          L = (nwg + S - 1) / S;
+          S = max(1, min(NT / Rp, (n + kPre - 1) / kPre));
+          L = (n + S - 1) / S;
           seg = threadIdx.x / Rp;
           rr = threadIdx.x - seg * Rp;
           j0 = seg < S ? seg * L : 0;
-          j1 = seg < S ? min(nwg, j0 + L) : 0;
+          j1 = seg < S ? min(n, j0 + L) : 0;
         }
         double acc = 0.0;
         if (seg < S) {
-          const double* wr = b.wpart + (size_t)(base + rr) * nwg;
+          const double* wr = rows + base + rr;  // partial j of the row at wr[j R]
           double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
           int j = j0;
           if (first) {
@@ -337,12 +341,12 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
           }
 #pragma unroll 4
           for (; j + 4 <= j1; j += 4) {
-            d0 += sc_lds[j] * wr[j];
-            d1 += sc_lds[j + 1] * wr[j + 1];
-            d2 += sc_lds[j + 2] * wr[j + 2];
-            d3 += sc_lds[j + 3] * wr[j + 3];
+            d0 += sc_lds[j] * wr[(size_t)j * R];
+            d1 += sc_lds[j + 1] * wr[(size_t)(j + 1) * R];
+            d2 += sc_lds[j + 2] * wr[(size_t)(j + 2) * R];
+            d3 += sc_lds[j + 3] * wr[(size_t)(j + 3) * R];
           }
-          for (; j < j1; ++j) d0 += sc_lds[j] * wr[j];
+          for (; j < j1; ++j) d0 += sc_lds[j] * wr[(size_t)j * R];
           acc = (d0 + d1) + (d2 + d3);
         }
         if (S > 1) {

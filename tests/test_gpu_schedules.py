@@ -32,6 +32,8 @@ def _run(cfg, U0, x0, iters, staged=False):
     ("cartpole_single", 1000, 37), ("cartpole_single", 65, 16), ("cartpole_single", 1, 5),
     ("quadrotor_hover", 700, 33), ("quadrotor_hover", 64, 3), ("double_integrator", 300, 100),
     ("cartpole_mpc", 4096, 100),
+    # wave-specialised fused updates with many partials per row
+    ("quadrotor_hover", 8192, 100), ("cartpole_mpc", 16384, 100), ("quadrotor_hover", 1100, 60),
 ])
 def test_schedules_and_update_paths_agree(preset, K, T):
     """Costs and perturbations agree bitwise.  The weights and the update sum
@@ -79,7 +81,7 @@ def test_large_K_uses_lane_schedule_and_staged_update():
 @pytest.mark.parametrize("preset,K,T,iters", [
     ("cartpole_mpc", 4096, 100, 5), ("quadrotor_hover", 1000, 37, 2),
     ("cartpole_single", 300, 1500, 2), ("double_integrator", 64, 1, 1),
-    ("cartpole_single", 150_000, 8, 2),
+    ("cartpole_single", 150_000, 8, 2), ("quadrotor_hover", 8192, 100, 2),
 ])
 def test_control_step_equals_step_then_shift(preset, K, T, iters):
     """The fused control step (shift and u_0 folded into the last
