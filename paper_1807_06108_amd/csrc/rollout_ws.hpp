@@ -16,12 +16,14 @@ namespace mppi {
 constexpr int kWsSamples = 64;  // samples per workgroup
 constexpr int kWsChunk = 16;    // time steps per ring slot
 
-// Wavefronts per workgroup: two per SIMD for the light models, so that a
-// producer shares each SIMD with another wave and latency is hidden; one per
-// SIMD for the 12-state model, whose consumer needs the larger register file.
+// Wavefronts per workgroup: eight (two per SIMD, one consumer and seven
+// producers).  Measured on the light models, 4, 6 and 12 are slower; for the
+// 12-state model eight waves cap the registers at 256 per lane (a few are
+// spilled) yet beat four waves with 512 (57.9 vs 60.3 us at K=8192, T=100):
+// with three producers it is the draws that bound the iteration.
 template <int DYN>
 struct WsWaves {
-  static constexpr int W = DYN == MPPI_DYN_QUADROTOR ? 4 : 8;
+  static constexpr int W = 8;
 };
 
 template <int DYN>
