@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define MPPI_JUMP_ABI_VERSION 2
+#define MPPI_JUMP_ABI_VERSION 3
 
 #define MPPI_JUMP_MAX_N 12      /* state dimension bound            */
 #define MPPI_JUMP_MAX_M 4       /* control dimension bound          */
@@ -127,6 +127,10 @@ typedef struct mppi_jump_config {
                             eps_D ~ N(0, Sigma_D)), row-major 4 x 4 of which
                             the leading m x m block is used: lower triangular,
                             diagonal > 0; sigma[] is then ignored            */
+  int32_t sample_offset; /* global index of this controller's first sample:
+                            sample k draws the noise of sample_offset + k, so
+                            controllers with disjoint offsets are shards of
+                            one larger sample set; >= 0, offset + K <= 2^31  */
 } mppi_jump_config;
 /* params: cartpole  = {m_cart, m_pole, half_length, g}
  *         quadrotor = {mass, Jx, Jy, Jz, arm, k_yaw, g, tilt_max, z_min}

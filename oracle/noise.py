@@ -130,13 +130,15 @@ def sample(cfg, iteration, k_index=None):
     """Standard-normal and count draws of one iteration.
 
     Returns z_D [K', T, m], N [K', T] (int32), z_J [K', T, q] for the samples
-    k_index (default: all K)."""
+    k_index (default: all K).  Sample k draws the stream of global sample
+    index sample_offset + k (a shard of a larger sample set)."""
     dyn = cfg["dynamics"]
     n, m, q, cw, nb = layout(dyn)
     K, T = cfg["K"], cfg["T"]
     if k_index is None:
         k_index = np.arange(K)
-    w = words(cfg["seed"], cfg["controller_id"], iteration, k_index, T, nb)
+    k_glob = int(cfg.get("sample_offset", 0)) + np.asarray(k_index, dtype=np.int64)
+    w = words(cfg["seed"], cfg["controller_id"], iteration, k_glob, T, nb)
     normals = []
     for p in range((m + q + 1) // 2):
         z0, z1 = box_muller(w[..., 2 * p], w[..., 2 * p + 1])

@@ -32,6 +32,7 @@ struct alignas(128) WgPartial {
 
 struct DevParams {
   int K, T, Ks, n_th;
+  uint32_t k0;                // global index of sample 0 (Philox counter)
   int wg_shift;               // log2 of the samples per rollout workgroup
   uint32_t key0, key1, ctr3;  // ctr3 = controller_id << 8
   int cost_form;
@@ -532,10 +533,10 @@ __device__ __forceinline__ void rollout_lane_tile(const DevParams& p, const Buff
   // software pipeline: the draws of step t + 1 are formed while step t's
   // dynamics run (they do not depend on the state)
   Noise<DYN, JUMPS> nxt;
-  draw_noise<DYN, JUMPS, FULL>(nxt, p, cs, 0u, (uint32_t)k, it);
+  draw_noise<DYN, JUMPS, FULL>(nxt, p, cs, 0u, p.k0 + (uint32_t)k, it);
   for (int t = 0; t < p.T; ++t) {
     const Noise<DYN, JUMPS> cur = nxt;
-    draw_noise<DYN, JUMPS, FULL>(nxt, p, cs, (uint32_t)(t + 1), (uint32_t)k, it);
+    draw_noise<DYN, JUMPS, FULL>(nxt, p, cs, (uint32_t)(t + 1), p.k0 + (uint32_t)k, it);
 
     // modified path cost, eqs. (34)-(35), on the pre-step state
     float u[M];

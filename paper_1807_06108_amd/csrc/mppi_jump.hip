@@ -114,6 +114,8 @@ int validate(const mppi_jump_config* c, int& n, int& m, int& q, std::vector<uint
   if (c->schedule < MPPI_SCHED_AUTO || c->schedule > MPPI_SCHED_WAVE_SPECIALISED)
     return fail(MPPI_EINVAL, "unknown schedule %d", c->schedule);
   if (c->full_sigma != 0 && c->full_sigma != 1) return fail(MPPI_EINVAL, "full_sigma must be 0 or 1");
+  if (c->sample_offset < 0 || (int64_t)c->sample_offset + c->K > (int64_t)1 << 31)
+    return fail(MPPI_EINVAL, "sample_offset must be >= 0 with sample_offset + K <= 2^31");
   if (c->full_sigma) {
     for (int i = 0; i < m; ++i)
       for (int j = 0; j < m; ++j) {
@@ -214,6 +216,7 @@ DevParams make_params(const mppi_jump_config* c, int n, int m, int q, const Layo
   p.T = c->T;
   p.Ks = L.Ks;
   p.wg_shift = L.ws ? 6 : 8;
+  p.k0 = (uint32_t)c->sample_offset;
   p.key0 = (uint32_t)(c->seed & 0xFFFFFFFFull);
   p.key1 = (uint32_t)(c->seed >> 32);
   p.ctr3 = (uint32_t)(c->controller_id << 8);

@@ -46,7 +46,7 @@ __device__ __forceinline__ void ws_produce(const DevParams& p, const Consts& cs,
   using Rg = WsRing<DYN>;
   constexpr int M = Md::M, Q = Md::Q;
   Noise<DYN, JUMPS> nz;
-  draw_noise<DYN, JUMPS, FULL>(nz, p, cs, (uint32_t)t, (uint32_t)k, it);
+  draw_noise<DYN, JUMPS, FULL>(nz, p, cs, (uint32_t)t, p.k0 + (uint32_t)k, it);
   float u[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) u[j] = U[t * M + j];

@@ -215,3 +215,12 @@ def test_full_covariance_validation():
     # a one-channel model: only L00 is read
     cp = workloads.cartpole(full_sigma=1, sigma_L=[1.5] + [0.0] * 15, sigma=[0.0] * 4)
     assert native.workspace_bytes(cp) > 0
+
+
+def test_sample_offset_validation():
+    assert native.workspace_bytes(workloads.cartpole(K=1000, sample_offset=5000)) > 0
+    for bad in (workloads.cartpole(K=1000, sample_offset=2**31 - 10),
+                workloads.cartpole(sample_offset=-1)):
+        with pytest.raises(native.MppiError) as e:
+            native.workspace_bytes(bad)
+        assert e.value.code == native.C["MPPI_EINVAL"]

@@ -338,3 +338,24 @@ def test_full_covariance_sample_covariance():
     e = eps.reshape(-1, 4)
     L = noise.cholesky_factor(cfg)
     assert np.abs(np.cov(e.T) - L @ L.T).max() < 0.05
+
+
+@pytest.mark.parametrize("preset", ["cartpole_single", "quadrotor_hover"])
+def test_shards_draw_the_unsharded_noise_and_combine_to_its_update(preset):
+    # Splitting the samples into shards with their global offsets gives the
+    # unsharded draws and costs, and the log-sum-exp combine of the shards'
+    # own updates (each normalised by its own eta) is the unsharded update.
+    from paper_1807_06108_amd import shard
+    cfg = workloads.PRESETS[preset](K=300, T=12)
+    x0 = workloads.x0_for(cfg)
+    U = workloads.U0_for(cfg, "random", seed=2).astype(np.float64)
+    full = mppi.iteration(cfg, x0, U, 3)
+    bounds = [0, 64, 200, 300]
+    parts = [mppi.iteration(dict(cfg, K=b - a, sample_offset=a), x0, U, 3)
+             for a, b in zip(bounds[:-1], bounds[1:])]
+    assert np.array_equal(np.concatenate([p["S"] for p in parts]), full["S"])
+    assert np.array_equal(np.concatenate([p["eps"] for p in parts]), full["eps"])
+    lam = float(np.float32(cfg["lambda"]))
+    U2 = shard.combine_updates(U, [p["U"] for p in parts], [p["rho"] for p in parts],
+                               [p["eta"] for p in parts], [p["status"] == 0 for p in parts], lam)
+    assert np.abs(U2 - full["U"]).max() < 1e-12
