@@ -26,6 +26,11 @@ struct BatchTile {
   int wg;
 };
 
+// The wave-specialised tiles here run four waves (one consumer, three
+// producers) in 256-thread blocks.  Eight waves, as in the single-controller
+// kernel, measured no faster over a mixed batch (the per-tile switch over
+// all twelve instantiations already costs the registers that the extra
+// producers would need, and the eight-wave build spills).
 template <bool WS>
 __device__ __forceinline__ void batch_tile(const BatchDesc& d, const float* x0, const ShiftArgs& sh,
                                            int wg) {

@@ -146,7 +146,7 @@ class Server:
     def _dist(self, ids):
         return np.stack([self.dist[c][self.served[c] % len(self.dist[c])] for c in ids])
 
-    def run(self, arrival_t, arrival_ctl, warmup_s=0.0, log=None):
+    def run(self, arrival_t, arrival_ctl, warmup_s=0.0):
         """Serve the request stream (times in s from the start of the call,
         controller index into the admitted set) in real time; returns the
         latency and throughput statistics of the requests that arrived after
