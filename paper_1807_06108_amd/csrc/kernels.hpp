@@ -126,10 +126,18 @@ constexpr int kStageRows = 1024;  // partial rows staged in LDS per pass
 //     the rescale exp(-(rho_wg - rho)/lambda) and, when FUSED, applies
 //     U[r] += alpha * sum_wg scale_wg P[r][wg] / eta (eqs. (36) / (49)) and
 //     advances the iteration counter.
+// Device-scope fences of the last-arrival pattern: the publishing side needs
+// only release (its stores before its arrival increment), the last arrival
+// only acquire (the others' stores before its loads).  A full fence would
+// add the other half: an L2 invalidate on the publishing side, a write-back
+// of this XCD's L2 on the combining side.
+__device__ __forceinline__ void release_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void acquire_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
 // Publication: every global partial is stored by wavefront 0, which then
 // issues the workgroup's single device-scope release fence before the
-// arrival counter is incremented (a device-scope fence writes back the L2 of
-// this XCD, so one per workgroup instead of one per wavefront).
+// arrival counter is incremented (a device-scope release writes back the L2
+// of this XCD, so one per workgroup instead of one per wavefront).
 // wg / nwg: this workgroup's index among the nwg workgroups of its controller.
 template <int SPW, bool FUSED, int NT = kBlock>
 __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffers& b, double Sd,
@@ -194,8 +202,8 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
             acc += ew[4 * j + 3] * (double)v.w;
           }
         }
-        acc += __shfl_xor(acc, 1, 64);
-        acc += __shfl_xor(acc, 2, 64);
+        acc += dpp_f64<kDppXor1>(acc);
+        acc += dpp_f64<kDppXor2>(acc);
         if (q == 0 && i < nrow) stage[i] = acc;
       }
       __syncthreads();
@@ -210,7 +218,7 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
       b.part[wg].eta = eta_wg;
       b.part[wg].nfin = (int32_t)nfin;
     }
-    __threadfence();
+    release_fence();
     if (lane == 0) {
       const uint32_t prev = atomicAdd(&b.counters[0], 1u);
       is_last = (prev == (uint32_t)nwg - 1);
@@ -218,7 +226,7 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
   }
   __syncthreads();
   if (!is_last) return;
-  __threadfence();
+  acquire_fence();
   const WgPartial* parts = b.part;
   const double* rows = b.wpart;  // row r of partial j at rows[j R + r]
   const int n = nwg;
@@ -227,7 +235,7 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
   // to spare, each row's partials are split into S contiguous segments, one
   // thread each.  The segment's first kPre partials and the row's U are
   // loaded now, so that their latency overlaps the statistics below.
-  constexpr int kPre = 8;
+  constexpr int kPre = 16;
   int Rp = 1, S = 1, L = 0, seg = 0, rr = 0, j0 = 0, j1 = 0;
   double wpre[kPre];
   float uold = 0.f;
@@ -642,13 +650,13 @@ __global__ __launch_bounds__(256) void update_kernel(const DevParams p, const Bu
     }
   }
   if (threadIdx.x == 0) {
-    __threadfence();
+    release_fence();
     const uint32_t prev = atomicAdd(&b.counters[1], 1u);
     is_last = (prev == gridDim.x * gridDim.y - 1);
   }
   __syncthreads();
   if (!is_last) return;
-  __threadfence();
+  acquire_fence();
   if (st.status == MPPI_OK) {
     const double scale = (double)p.alpha / st.eta;
     for (int r = threadIdx.x; r < R; r += kBlock) {
