@@ -26,6 +26,35 @@ struct WsWaves {
   static constexpr int W = 8;
 };
 
+// Steps of a chunk per producer wave with eight waves.  The waves of a
+// workgroup sit on the four SIMDs round-robin, so wave 4 shares SIMD 0 with
+// the consumer: it takes MATE steps and the rest are split evenly over
+// SIMDs 1-3 (waves 1 and 5, 2 and 6, 3 and 7), each wave a contiguous range.
+// On the light models the consumer's recursion sets the pace and its mate
+// takes one step (measured: 0 and 2 are slower); the 12-state model's three
+// draw blocks per step make the producers the bound, and its mate keeps an
+// even share (two steps: the per-wave counts of a round-robin split).
+template <int DYN>
+struct WsSplit {
+  static constexpr int MATE = DYN == MPPI_DYN_QUADROTOR ? 2 : 1;
+  __host__ __device__ static constexpr int count(int w) {
+    if (w <= 0 || w > 7) return 0;
+    if (w == 4) return MATE;
+    const int rem = kWsChunk - MATE;
+    const int simd = w & 3;  // 1..3
+    const int n = rem / 3 + (simd - 1 < rem % 3 ? 1 : 0);
+    return w < 4 ? (n + 1) / 2 : n / 2;
+  }
+  __host__ __device__ static constexpr int first(int w) {
+    int f = 0;
+    for (int v = 1; v < w; ++v) f += count(v);
+    return f;
+  }
+};
+static_assert(WsSplit<MPPI_DYN_CARTPOLE>::first(8) == kWsChunk, "split covers the chunk");
+static_assert(WsSplit<MPPI_DYN_QUADROTOR>::first(8) == kWsChunk, "split covers the chunk");
+static_assert(WsSplit<MPPI_DYN_LINEAR>::first(8) == kWsChunk, "split covers the chunk");
+
 template <int DYN>
 struct WsRing {
   using Md = Model<DYN>;
@@ -157,10 +186,20 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
     if (wave > 0) {
       if (c < nch) {
         float(*buf)[SLOT] = ring[c & 1];
-        for (int s = wave - 1; s < kWsChunk; s += NP) {
-          const int t = c * kWsChunk + s;
-          if (t < T)
-            ws_produce<DYN, JUMPS, DEBUG, FORM, FULL>(p, cs, b, U, buf[s], t, k, active, it);
+        if constexpr (W == 8) {
+          const int w = __builtin_amdgcn_readfirstlane(wave);
+          const int s0 = WsSplit<DYN>::first(w), s1 = s0 + WsSplit<DYN>::count(w);
+          for (int s = s0; s < s1; ++s) {
+            const int t = c * kWsChunk + s;
+            if (t < T)
+              ws_produce<DYN, JUMPS, DEBUG, FORM, FULL>(p, cs, b, U, buf[s], t, k, active, it);
+          }
+        } else {
+          for (int s = wave - 1; s < kWsChunk; s += NP) {
+            const int t = c * kWsChunk + s;
+            if (t < T)
+              ws_produce<DYN, JUMPS, DEBUG, FORM, FULL>(p, cs, b, U, buf[s], t, k, active, it);
+          }
         }
       }
     } else if (c > 0) {
