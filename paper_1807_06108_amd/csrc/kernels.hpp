@@ -280,13 +280,20 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
       }
     }
   } else {
-    double m = INFINITY;
-    for (int j = threadIdx.x; j < n; j += NT)
-      if (parts[j].nfin > 0) m = fmin(m, parts[j].rho);
+    // a thread's first partial stays in registers across both passes, loaded
+    // whole and unconditionally (one memory round trip, not a dependent load
+    // per field); further ones (unfused statistics of very large K) reload
+    WgPartial q0{INFINITY, 0.0, 0};
+    if (threadIdx.x < n) q0 = parts[threadIdx.x];
+    double m = q0.nfin > 0 ? q0.rho : INFINITY;
+    for (int j = threadIdx.x + NT; j < n; j += NT) {
+      const WgPartial q = parts[j];
+      m = q.nfin > 0 ? fmin(m, q.rho) : m;
+    }
     const double rho = block_min<NW>(m, lds);
     double eta = 0.0, cnt = 0.0;
     for (int j = threadIdx.x; j < n; j += NT) {
-      const WgPartial q = parts[j];
+      const WgPartial q = j < NT ? q0 : parts[j];
       const double sc = (q.nfin > 0) ? exp(-(q.rho - rho) / p.lam_d) : 0.0;
       b.scale[j] = sc;
       if constexpr (FUSED) sc_lds[j] = sc;

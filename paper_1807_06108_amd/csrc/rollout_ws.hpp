@@ -175,6 +175,14 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
   __shared__ Consts cs;
   stage_consts(cs, p);
 
+  // eight waves: this producer's contiguous range of each chunk's steps
+  int s0 = 0, s1 = 0;
+  if constexpr (W == 8) {
+    const int w = __builtin_amdgcn_readfirstlane(wave);
+    s0 = WsSplit<DYN>::first(w);
+    s1 = s0 + WsSplit<DYN>::count(w);
+  }
+
   WsState<DYN> st;
 #pragma unroll
   for (int i = 0; i < N; ++i) st.x[i] = x0[i];
@@ -187,8 +195,6 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
       if (c < nch) {
         float(*buf)[SLOT] = ring[c & 1];
         if constexpr (W == 8) {
-          const int w = __builtin_amdgcn_readfirstlane(wave);
-          const int s0 = WsSplit<DYN>::first(w), s1 = s0 + WsSplit<DYN>::count(w);
           for (int s = s0; s < s1; ++s) {
             const int t = c * kWsChunk + s;
             if (t < T)
