@@ -355,6 +355,23 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
               j = j1;
             }
           }
+          // the rest in batches of kBatch loads issued together (one memory
+          // round trip each), accumulated in the same pattern as below; only
+          // in the eight-wave workgroups, which have the registers to spare
+          // (the 256-thread kernels would lose occupancy)
+          constexpr int kBatch = NT >= 512 ? 32 : 4;
+          for (; NT >= 512 && j + kBatch <= j1; j += kBatch) {
+            double w[kBatch];
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) w[q] = wr[(size_t)(j + q) * R];
+#pragma unroll
+            for (int q = 0; q < kBatch; q += 4) {
+              d0 += sc_lds[j + q] * w[q];
+              d1 += sc_lds[j + q + 1] * w[q + 1];
+              d2 += sc_lds[j + q + 2] * w[q + 2];
+              d3 += sc_lds[j + q + 3] * w[q + 3];
+            }
+          }
 #pragma unroll 4
           for (; j + 4 <= j1; j += 4) {
             d0 += sc_lds[j] * wr[(size_t)j * R];
