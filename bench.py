@@ -23,7 +23,11 @@ The JSON line also carries
                    MPC-step requests/s: p50/p99 latency (arrival to u0 on the
                    host) of pooled ticks against per-controller launches, and
                    the capacity of each back end,
-  cpu_baseline     the FP64 oracle on a bounded sample of the same loop.
+  cpu_baseline     the FP64 oracle on a bounded sample of the same loop, one
+                   thread,
+  cpu_baseline_all_cores
+                   the same with each iteration's samples split over the host
+                   cores (worker processes).
 """
 
 import argparse
@@ -106,10 +110,67 @@ def cpu_baseline(cfg, x0, U0, iters, dist, budget_s):
             break
     el = time.perf_counter() - t0
     return dict(value=cfg["K"] * cfg["T"] * iters * steps / el, unit="rollout-steps/s",
-                cores=1, kind="oracle",
+                cores=1, kind="oracle", cpu=host_cpu(),
                 sample="%d closed-loop control steps of this workload (%d iterations each, "
                        "K=%d, T=%d), %.1f s, single thread" % (steps, iters, cfg["K"],
                                                                cfg["T"], el))
+
+
+def host_cpu():
+    """Model name of the host processor (first entry of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_all_cores(cfg, x0, U0, iters, dist, budget_s, workers):
+    """The same oracle with each iteration's samples split over `workers`
+    processes (oracle.shards: the parent forms the weights and update;
+    results equal the one-thread oracle).  Workers start from a fresh
+    interpreter (no GPU state) with one BLAS thread each; their start-up is
+    not timed.  A worker that dies raises (BrokenProcessPool) instead of
+    being replaced."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    from oracle import models, shards
+    from oracle import mppi as omppi
+    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in keys}
+    x = x0.astype(np.float64)
+    U = U0.astype(np.float64)
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as pool:
+        for k in keys:
+            os.environ[k] = "1"
+        try:
+            shards.iteration_U(pool, workers, cfg, x, U, 0)  # starts the workers
+        finally:
+            for k, v in saved.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+        P = omppi.f32(cfg["params"])
+        dt = float(omppi.f32(cfg["dt"]))
+        t0 = time.perf_counter()
+        steps = 0
+        while True:
+            u0, U = shards.control_step(pool, workers, cfg, x, U, steps * iters, iters)
+            x = models.euler_step(cfg["dynamics"], x[None], (u0 + dist[steps])[None],
+                                  np.zeros((1, 3)), dt, P)[0]
+            steps += 1
+            if time.perf_counter() - t0 > budget_s or steps >= len(dist):
+                break
+        el = time.perf_counter() - t0
+    return dict(value=cfg["K"] * cfg["T"] * iters * steps / el, unit="rollout-steps/s",
+                cores=workers, kind="oracle", cpu=host_cpu(),
+                sample="%d closed-loop control steps of this workload, each iteration's "
+                       "K=%d samples split over %d worker processes, %.1f s"
+                       % (steps, cfg["K"], workers, el))
 
 
 def batched_measure(n_ctl, ticks, warmup, seed=42):
@@ -247,6 +308,9 @@ def main():
                     help="rollout schedule (identical results)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-workers", type=int, default=None,
+                    help="worker processes of the all-cores oracle timing (default: the "
+                         "usable host cores, at most 16; 0 skips it)")
     ap.add_argument("--host-loop-steps", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--batched-controllers", type=int, default=256)
@@ -385,6 +449,17 @@ def main():
         line["cpu_baseline"] = cpu_baseline(cfg, x0, U0, iters,
                                             dist[args.warmup:].astype(np.float64),
                                             args.cpu_budget)
+        workers = args.cpu_workers
+        if workers is None:
+            workers = min(16, len(os.sched_getaffinity(0)))
+        if workers > 1:
+            progress("oracle on %d host cores (about %.0f s)" % (workers, args.cpu_budget / 2))
+            try:
+                line["cpu_baseline_all_cores"] = cpu_baseline_all_cores(
+                    cfg, x0, U0, iters, dist[args.warmup:].astype(np.float64),
+                    args.cpu_budget / 2, workers)
+            except Exception as e:  # the GPU figures stand without it
+                line["cpu_baseline_all_cores"] = {"error": repr(e)}
     print(json.dumps(line), flush=True)
 
 

@@ -359,3 +359,38 @@ def test_shards_draw_the_unsharded_noise_and_combine_to_its_update(preset):
     U2 = shard.combine_updates(U, [p["U"] for p in parts], [p["rho"] for p in parts],
                                [p["eta"] for p in parts], [p["status"] == 0 for p in parts], lam)
     assert np.abs(U2 - full["U"]).max() < 1e-12
+
+
+@pytest.mark.parametrize("preset,K,T,nshards", [("cartpole_single", 37, 9, 3),
+                                                ("quadrotor_hover", 20, 6, 4)])
+def test_sample_sharded_oracle_equals_the_oracle(preset, K, T, nshards):
+    # The all-cores timing of the oracle splits each iteration's samples over
+    # worker processes and forms the weights and update in the parent; every
+    # sample's draws and cost depend on that sample alone, so the control
+    # step is exactly the unsharded one (ragged shards included).
+    from oracle import shards
+    cfg = workloads.PRESETS[preset](K=K, T=T)
+    x0 = workloads.x0_for(cfg).astype(np.float64)
+    U0 = workloads.U0_for(cfg, "random").astype(np.float64)
+    u0_ref, U_ref = mppi.control_step(cfg, x0, U0, 5, 2)
+    u0_a, U_a = shards.control_step(map_pool(), nshards, cfg, x0, U0, 5, 2)
+    assert np.array_equal(U_a, U_ref) and np.array_equal(u0_a, u0_ref)
+
+
+def test_sample_sharded_oracle_in_worker_processes():
+    import multiprocessing as mp
+    from oracle import shards
+    cfg = workloads.PRESETS["cartpole_single"](K=30, T=7)
+    x0 = workloads.x0_for(cfg).astype(np.float64)
+    U0 = workloads.U0_for(cfg, "random").astype(np.float64)
+    with mp.get_context("spawn").Pool(2) as pool:
+        u0_a, U_a = shards.control_step(pool, 2, cfg, x0, U0, 0, 1)
+    u0_ref, U_ref = mppi.control_step(cfg, x0, U0, 0, 1)
+    assert np.array_equal(U_a, U_ref) and np.array_equal(u0_a, u0_ref)
+
+
+class map_pool:
+    """In-process stand-in for a process pool."""
+
+    def map(self, fn, jobs):
+        return [fn(j) for j in jobs]
