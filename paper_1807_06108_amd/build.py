@@ -36,18 +36,24 @@ def build(extra_flags=(), out=LIB, verbose=False):
     return out
 
 
-PROBE_SRC = os.path.join(HERE, "probe", "issue_rates.hip")
-PROBE_BIN = os.path.join(HERE, "probe", "issue_rates")
+# Measurement probes (executables for gfx950): VALU issue rates, dependent
+# latencies, and the SIMD placement of a workgroup's wavefronts.
+PROBES = ("issue_rates", "dep_latency", "wave_placement")
 
 
 def build_probe(verbose=False):
-    """Compile the VALU issue-rate probe (an executable for gfx950)."""
-    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature", "-Xclang",
-           "-packed-fp32-ops", "-o", PROBE_BIN, PROBE_SRC]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    return PROBE_BIN
+    """Compile the measurement probes; returns their paths."""
+    out = []
+    for name in PROBES:
+        src = os.path.join(HERE, "probe", name + ".hip")
+        bin_ = os.path.join(HERE, "probe", name)
+        cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-Xclang", "-target-feature", "-Xclang",
+               "-packed-fp32-ops", "-o", bin_, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        out.append(bin_)
+    return out
 
 
 if __name__ == "__main__":
