@@ -116,6 +116,14 @@ __device__ __forceinline__ void stage_consts(Consts& cs, const DevParams& p) {
 constexpr int kFusedMaxWg = 512;
 constexpr int kStageRows = 1024;  // partial rows staged in LDS per pass
 
+// Device-scope fences of the last-arrival pattern: the publishing side needs
+// only release (its stores before its arrival increment), the last arrival
+// only acquire (the others' stores before its loads).  A full fence would
+// add the other half: an L2 invalidate on the publishing side, a write-back
+// of this XCD's L2 on the combining side.
+__device__ __forceinline__ void release_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void acquire_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
+
 // Rollout epilogue over the SPW samples of this workgroup (threads below SPW
 // hold a cost; the others pass active = false):
 //   * statistics of eq. (37): rho_wg = min of the finite S_k, E_k =
@@ -126,14 +134,6 @@ constexpr int kStageRows = 1024;  // partial rows staged in LDS per pass
 //     the rescale exp(-(rho_wg - rho)/lambda) and, when FUSED, applies
 //     U[r] += alpha * sum_wg scale_wg P[r][wg] / eta (eqs. (36) / (49)) and
 //     advances the iteration counter.
-// Device-scope fences of the last-arrival pattern: the publishing side needs
-// only release (its stores before its arrival increment), the last arrival
-// only acquire (the others' stores before its loads).  A full fence would
-// add the other half: an L2 invalidate on the publishing side, a write-back
-// of this XCD's L2 on the combining side.
-__device__ __forceinline__ void release_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
-__device__ __forceinline__ void acquire_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
-
 // Publication: every global partial is stored by wavefront 0, which then
 // issues the workgroup's single device-scope release fence before the
 // arrival counter is incremented (a device-scope release writes back the L2
