@@ -110,6 +110,7 @@ def cpu_baseline(cfg, x0, U0, iters, dist, budget_s):
             break
     el = time.perf_counter() - t0
     return dict(value=cfg["K"] * cfg["T"] * iters * steps / el, unit="rollout-steps/s",
+                ms_per_control_step=1e3 * el / steps,
                 cores=1, kind="oracle", cpu=host_cpu(),
                 sample="%d closed-loop control steps of this workload (%d iterations each, "
                        "K=%d, T=%d), %.1f s, single thread" % (steps, iters, cfg["K"],
@@ -167,6 +168,7 @@ def cpu_baseline_all_cores(cfg, x0, U0, iters, dist, budget_s, workers):
                 break
         el = time.perf_counter() - t0
     return dict(value=cfg["K"] * cfg["T"] * iters * steps / el, unit="rollout-steps/s",
+                ms_per_control_step=1e3 * el / steps,
                 cores=workers, kind="oracle", cpu=host_cpu(),
                 sample="%d closed-loop control steps of this workload, each iteration's "
                        "K=%d samples split over %d worker processes, %.1f s"
