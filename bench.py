@@ -47,7 +47,7 @@ import numpy as np  # noqa: E402
 # slots of the gfx950 instruction that implements it (full rate 1; 32x32->64
 # multiply and transcendental 4, as measured by the instruction-rate probe).
 # Derivation in the design notes (rollout roofline section).
-ALG_SLOTS = {0: 187, 1: 219, 2: 653}
+ALG_SLOTS = {0: 187, 1: 219, 2: 537}
 ALG_FP32_FLOP = {0: 40, 1: 71, 2: 231}
 # 256 CUs x 128 full-rate lane-slots per CU-clock x 2.4 GHz (measured issue
 # rate of v_fma_f32; at 2 FLOP per slot this is the 157.3 TFLOP/s FP32 peak)

@@ -23,9 +23,14 @@ Normal number i comes from the Box-Muller pair i // 2 (words 2p, 2p+1):
   u = ((w[2p] >> 8) + 1) / 2^24 in (0, 1]     (radius: -2 ln u finite)
   v =  (w[2p+1] >> 8)     / 2^24 in [0, 1)    (angle: 2 pi v)
   normal 2p = sqrt(-2 ln u) cos(2 pi v), normal 2p+1 = sqrt(-2 ln u) sin(2 pi v)
-(Box & Muller 1958).  The first m normals are z_D, the next q are z_J, and
-the word after the last pair is the jump-count word: the count is the number
-of integer thresholds theta_0 <= theta_1 <= ... that the 32-bit word reaches,
+(Box & Muller 1958).  The first m normals are z_D, the next q are z_J.  The
+jump-count word is the word after the last pair when that word lies in a
+block the pairs already use (one- and two-channel models: word 2); when the
+pairs fill whole blocks (the quadrotor: 4 pairs, words 0-7, two blocks) it is
+assembled from the low bytes of words 0-3, which Box-Muller leaves unused:
+  w_count = (w[0] & 255) | (w[1] & 255) << 8 | (w[2] & 255) << 16 | (w[3] & 255) << 24
+so that no block is drawn for one word.  The count is the number of integer
+thresholds theta_0 <= theta_1 <= ... that the 32-bit word reaches,
 theta_j = floor(F(j) * 2^32) with F the CDF of the count law (inversion; the
 decision is taken in integers, so both implementations agree exactly).
 
@@ -51,12 +56,23 @@ JUMP_IN_CONTROL = {0: True, 1: True, 2: False}
 
 
 def layout(dynamics):
-    """(n, m, q, count_word, n_blocks) of the per-(k, t) word stream."""
+    """(n, m, q, count_word, n_blocks) of the per-(k, t) word stream;
+    count_word is None when the count word is assembled from low bytes."""
     n, m, q = DIMS[dynamics]
     pairs = (m + q + 1) // 2
+    if (2 * pairs) % 4 == 0:
+        return n, m, q, None, 2 * pairs // 4
     count_word = 2 * pairs
     n_blocks = count_word // 4 + 1
     return n, m, q, count_word, n_blocks
+
+
+def low_byte_word(w):
+    """Count word from the low bytes of words 0-3 of the stream (uint32)."""
+    w = w.astype(np.uint64)
+    out = (w[..., 0] & 255) | ((w[..., 1] & 255) << 8) | ((w[..., 2] & 255) << 16) \
+        | ((w[..., 3] & 255) << 24)
+    return out.astype(np.uint32)
 
 
 def words(seed, controller_id, iteration, k_index, T, n_blocks):
@@ -146,7 +162,8 @@ def sample(cfg, iteration, k_index=None):
     z_D = np.stack(normals[:m], axis=-1)
     z_J = np.stack(normals[m:m + q], axis=-1)
     a = float(np.float32(cfg["nu"])) * float(np.float32(cfg["dt"]))
-    N = counts(w[..., cw], count_thresholds(a, cfg.get("count_law", 0)))
+    wc = low_byte_word(w) if cw is None else w[..., cw]
+    N = counts(wc, count_thresholds(a, cfg.get("count_law", 0)))
     return z_D, N, z_J
 
 

@@ -435,7 +435,9 @@ template <int DYN, bool JUMPS>
 struct Noise {
   using Md = Model<DYN>;
   static constexpr int NN = JUMPS ? Md::M + Md::Q : Md::M;   // normals needed
-  static constexpr int NW = JUMPS ? Md::COUNT_WORD + 1 : 2 * ((Md::M + 1) / 2);
+  static constexpr int NW = !JUMPS               ? 2 * ((Md::M + 1) / 2)
+                            : Md::COUNT_WORD < 0 ? 2 * ((Md::M + Md::Q + 1) / 2)
+                                                 : Md::COUNT_WORD + 1;
   static constexpr int NB = (NW + 3) / 4;                     // Philox blocks
   float z[NN + 1];
   float eps[Md::M];
@@ -483,7 +485,15 @@ __device__ __forceinline__ void draw_noise(Noise<DYN, JUMPS>& o, const DevParams
   o.gust[0] = o.gust[1] = o.gust[2] = 0.f;
   o.n = 0;
   if constexpr (JUMPS) {
-    o.n = jump_count(w[Md::COUNT_WORD], cs.th, p.th, p.n_th);
+    // count word: the word after the last Box-Muller pair, or, when the
+    // pairs fill whole blocks (COUNT_WORD < 0), the low bytes of words 0-3,
+    // which Box-Muller does not use (it takes the top 24 bits of a word)
+    uint32_t wc;
+    if constexpr (Md::COUNT_WORD < 0)
+      wc = (w[0] & 255u) | (w[1] & 255u) << 8 | (w[2] & 255u) << 16 | w[3] << 24;
+    else
+      wc = w[Md::COUNT_WORD];
+    o.n = jump_count(wc, cs.th, p.th, p.n_th);
     const float sq = __builtin_amdgcn_sqrtf((float)o.n);
     if constexpr (Md::JUMP_IN_CONTROL) {
 #pragma unroll

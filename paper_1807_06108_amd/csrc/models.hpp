@@ -90,7 +90,8 @@ struct Model<MPPI_DYN_CARTPOLE> {
 template <>
 struct Model<MPPI_DYN_QUADROTOR> {
   static constexpr int N = 12, M = 4, Q = 3;
-  static constexpr int NBLK = 3, COUNT_WORD = 8;
+  // 7 normals fill two blocks; the count word takes their unused low bytes
+  static constexpr int NBLK = 2, COUNT_WORD = -1;
   static constexpr bool JUMP_IN_CONTROL = false;
   static constexpr bool CAN_CRASH = true;
 

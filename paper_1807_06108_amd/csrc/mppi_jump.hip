@@ -735,7 +735,7 @@ int batch_check(mppi_jump_ctx* const* ctxs, int32_t n, BatchLayout& BL, bool& ws
 // Tile cost estimate for the longest-first order: time steps times the
 // issue slots of one sample-step of the model.
 double tile_cost(const mppi_jump_ctx* c) {
-  const double per_step = c->cfg.dynamics == MPPI_DYN_QUADROTOR ? 653.0
+  const double per_step = c->cfg.dynamics == MPPI_DYN_QUADROTOR ? 537.0
                           : c->cfg.dynamics == MPPI_DYN_CARTPOLE ? 219.0 : 187.0;
   return per_step * c->cfg.T;
 }

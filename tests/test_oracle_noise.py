@@ -132,7 +132,7 @@ def test_zero_one_mixture_density_eq42():
 
 
 def test_quadrotor_layout_and_gust():
-    assert noise.layout(2) == (12, 4, 3, 8, 3)
+    assert noise.layout(2) == (12, 4, 3, None, 2)
     assert noise.layout(1) == (4, 1, 1, 2, 1)
     cfg = workloads.quadrotor(K=512, T=40)
     z_D, N, z_J = noise.sample(cfg, 0)
@@ -156,3 +156,34 @@ def test_stream_properties():
     for over in (dict(controller_id=1), dict(seed=cfg["seed"] + 1)):
         assert not np.array_equal(noise.sample(dict(cfg, **over), 4)[0], zD)
     assert not np.array_equal(noise.sample(cfg, 5)[0], zD)
+
+
+def test_low_byte_count_word_is_poisson_and_independent():
+    # quadrotor: the count word comes from the low bytes of words 0-3, the
+    # same words whose top 24 bits give z_D.  The counts must still follow
+    # the count law (chi-square against scipy's Poisson pmf) and carry no
+    # dependence on the Gaussian draws of their step.
+    cfg = workloads.quadrotor(K=4096, T=50, nu=40.0)
+    z_D, N, _ = noise.sample(cfg, 2)
+    a = float(np.float32(40.0)) * float(np.float32(cfg["dt"]))
+    n = N.ravel()
+    top = 5
+    obs = np.array([np.sum(n == j) for j in range(top)] + [np.sum(n >= top)], dtype=np.float64)
+    pmf = stats.poisson.pmf(np.arange(top), a)
+    exp = n.size * np.append(pmf, 1.0 - pmf.sum())
+    assert stats.chisquare(obs, exp).pvalue > 1e-4
+    # mean and variance a; no correlation with z_D or z_D^2
+    assert abs(n.mean() - a) < 5 * math.sqrt(a / n.size)
+    for j in range(4):
+        for f in (z_D[..., j], z_D[..., j] ** 2):
+            r = np.corrcoef(n, f.ravel())[0, 1]
+            assert abs(r) < 5 / math.sqrt(n.size)
+    # the assembled word is uniform over 32 bits: its byte lanes are
+    # the low bytes of four different words
+    w = noise.words(cfg["seed"], cfg["controller_id"], 2, np.arange(256), 50, 2)
+    wc = noise.low_byte_word(w)
+    for sh in (0, 8, 16, 24):
+        b = ((wc >> sh) & 255).ravel()
+        assert np.array_equal(b, (w[..., sh // 8] & 255).ravel())
+        hist = np.bincount(b, minlength=256).astype(np.float64)
+        assert stats.chisquare(hist).pvalue > 1e-4
