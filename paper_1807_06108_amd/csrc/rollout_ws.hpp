@@ -31,9 +31,10 @@ struct WsWaves {
 // the consumer: it takes MATE steps and the rest are split evenly over
 // SIMDs 1-3 (waves 1 and 5, 2 and 6, 3 and 7), each wave a contiguous range.
 // On the light models the consumer's recursion sets the pace and its mate
-// takes one step (measured: 0 and 2 are slower); the 12-state model's three
-// draw blocks per step make the producers the bound, and its mate keeps an
-// even share (two steps: the per-wave counts of a round-robin split).
+// takes one step (measured: 0 and 2 are slower); the 12-state model's two
+// draw blocks per step keep the producers close to the consumer's pace, and
+// its mate keeps an even share (two steps: the per-wave counts of a
+// round-robin split; one step measures the same, three are slower).
 template <int DYN>
 struct WsSplit {
   static constexpr int MATE = DYN == MPPI_DYN_QUADROTOR ? 2 : 1;
