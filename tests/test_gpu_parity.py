@@ -36,12 +36,21 @@ def test_device_philox_is_bitwise_the_oracle():
     ("cartpole_single", {}), ("cartpole_single", dict(count_law=1, nu=10.0)),
     ("quadrotor_hover", dict(K=512, T=40)), ("double_integrator", {}),
     ("cartpole_single", dict(nu=0.0)),
+    # the quadrotor's count word is built from the low bytes of words 0-3:
+    # jump means where many counts are non-zero, both laws, both schedules
+    ("quadrotor_hover", dict(K=300, T=40, nu=40.0)),
+    ("quadrotor_hover", dict(K=300, T=40, nu=40.0, schedule=native.C["MPPI_SCHED_LANE"])),
+    ("quadrotor_hover", dict(K=300, T=40, count_law=1, nu=40.0)),
+    ("quadrotor_hover", dict(K=300, T=40, count_law=1, nu=40.0,
+                             schedule=native.C["MPPI_SCHED_LANE"])),
 ])
 def test_noise_draws_match_oracle(preset, over):
     cfg = workloads.PRESETS[preset](debug_dump=1, **over)
     ctl, ref, _, _ = run_rollout(cfg)
     zD, N, zJ = [t.cpu().numpy() for t in ctl.debug_draws()]
     assert np.array_equal(N, ref["N"])
+    if cfg["nu"] * cfg["dt"] > 0.3:
+        assert (N > 0).mean() > 0.2
     assert np.abs(zD - ref["z_D"]).max() < 1e-5
     if cfg["nu"] > 0:
         assert np.abs(zJ - ref["z_J"]).max() < 1e-5
