@@ -75,12 +75,17 @@ def params(cfg):
         u_init=f32(cfg["u_init"][:m]))
 
 
-def rollout(cfg, x0, U, eps, gust):
+def rollout(cfg, x0, U, eps, gust, with_magnitude=False):
     """Path costs S~_k of eq. (34) for the perturbations eps [K', T, m] and
     body-force disturbances gust [K', T, 3].
 
     Returns (S [K'], crash_margin [K']); the margin is the smallest distance
-    of any visited quadrotor state to the crash boundary (inf otherwise)."""
+    of any visited quadrotor state to the crash boundary (inf otherwise).
+    with_magnitude: also the sum of the magnitudes of the terms that make up
+    each S~_k (every running-cost, control-cost and importance-sampling term
+    and the terminal cost), the scale against which the rounding of a sum of
+    signed terms is measured: the IS cross term of eq. (35) is signed, so S~
+    can be far smaller than its terms."""
     p = params(cfg)
     dyn = cfg["dynamics"]
     Kp, T, m = eps.shape
@@ -88,6 +93,7 @@ def rollout(cfg, x0, U, eps, gust):
     x = np.repeat(f32(x0)[None, :p["n"]], Kp, axis=0)
     U = np.asarray(U, dtype=np.float64).reshape(T, m)
     S = np.zeros(Kp)
+    Sabs = np.zeros(Kp)
     crashed = np.zeros(Kp, dtype=bool)
     margin = np.full(Kp, np.inf)
     if dyn == 2:
@@ -106,8 +112,10 @@ def rollout(cfg, x0, U, eps, gust):
                 is_cross = lam * c * (e @ (p["Pinv"] @ U[t]))
                 is_var = 0.5 * lam * (c - 1.0) * np.einsum("ki,ij,kj->k", e, p["Pinv"], e)
             S = S + (qx + ctrl) * dt + is_cross + is_var
+            Sabs = Sabs + (np.abs(qx) + abs(ctrl)) * dt + np.abs(is_cross) + np.abs(is_var)
         else:
             S = S + (qx + 0.5 * (p["R"] * v * v).sum(axis=1)) * dt
+            Sabs = Sabs + (np.abs(qx) + 0.5 * (np.abs(p["R"]) * v * v).sum(axis=1)) * dt
         xn = models.euler_step(dyn, x, v, gust[:, t, :], dt, p["P"])
         if dyn == 2:
             xn = np.where(crashed[:, None], x, xn)
@@ -115,7 +123,10 @@ def rollout(cfg, x0, U, eps, gust):
                                                  models.quadrotor_margin(xn, p["P"])))
             crashed = crashed | models.quadrotor_crashed(xn, p["P"])
         x = xn
-    S = S + models.state_cost(x, p["Qf"], p["goal"]) + p["pen"] * crashed
+    phi = models.state_cost(x, p["Qf"], p["goal"]) + p["pen"] * crashed
+    S = S + phi
+    if with_magnitude:
+        return S, margin, Sabs + np.abs(phi)
     return S, margin
 
 
@@ -142,8 +153,8 @@ def iteration(cfg, x0, U, it, k_index=None):
     """One full iteration with the method's own noise draws (Philox)."""
     z_D, N, z_J = noise.sample(cfg, it, k_index)
     eps, gust = noise.compose(cfg, z_D, N, z_J)
-    S, margin = rollout(cfg, x0, U, eps, gust)
-    out = dict(z_D=z_D, N=N, z_J=z_J, eps=eps, gust=gust, S=S, margin=margin)
+    S, margin, S_abs = rollout(cfg, x0, U, eps, gust, with_magnitude=True)
+    out = dict(z_D=z_D, N=N, z_J=z_J, eps=eps, gust=gust, S=S, margin=margin, S_abs=S_abs)
     if k_index is None:
         w, rho, eta, status = weights(S, float(f32(cfg["lambda"])))
         U = np.asarray(U, dtype=np.float64).reshape(cfg["T"], -1)

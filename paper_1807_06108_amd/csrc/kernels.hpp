@@ -552,11 +552,13 @@ __device__ __forceinline__ float state_free_cost(const DevParams& p, const Const
 // FORM: MPPI_COST_IT or MPPI_COST_SO.  FUSED: the epilogue also applies the
 // update (one kernel per iteration); otherwise it only forms the statistics
 // and update_kernel follows.
-// One workgroup (tile wg of nwg) of the one-sample-per-lane rollout.
+// One workgroup (tile wg of nwg) of the one-sample-per-lane rollout.  U is
+// not restrict-qualified: in the fused form the last workgroup writes the
+// same array (through b.U) while the kernel runs.
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL = false>
 __device__ __forceinline__ void rollout_lane_tile(const DevParams& p, const Buffers& b,
                                                   const float* __restrict__ x0,
-                                                  const float* __restrict__ U, int R,
+                                                  const float* U, int R,
                                                   const ShiftArgs& sh, int wg, int nwg) {
   using Md = Model<DYN>;
   constexpr int N = Md::N, M = Md::M, Q = Md::Q;
@@ -573,12 +575,14 @@ __device__ __forceinline__ void rollout_lane_tile(const DevParams& p, const Buff
   float S = 0.f, comp = 0.f;
 
   // software pipeline: the draws of step t + 1 are formed while step t's
-  // dynamics run (they do not depend on the state)
+  // dynamics run (they do not depend on the state); the last step draws
+  // nothing ahead
   Noise<DYN, JUMPS> nxt;
   draw_noise<DYN, JUMPS, FULL>(nxt, p, cs, 0u, p.k0 + (uint32_t)k, it);
   for (int t = 0; t < p.T; ++t) {
     const Noise<DYN, JUMPS> cur = nxt;
-    draw_noise<DYN, JUMPS, FULL>(nxt, p, cs, (uint32_t)(t + 1), p.k0 + (uint32_t)k, it);
+    if (t + 1 < p.T)
+      draw_noise<DYN, JUMPS, FULL>(nxt, p, cs, (uint32_t)(t + 1), p.k0 + (uint32_t)k, it);
 
     // modified path cost, eqs. (34)-(35), on the pre-step state
     float u[M];
@@ -640,7 +644,7 @@ __device__ __forceinline__ void rollout_lane_tile(const DevParams& p, const Buff
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL>
 __global__ __launch_bounds__(256) void rollout_kernel(const DevParams p, const Buffers b,
                                                       const float* __restrict__ x0,
-                                                      const float* __restrict__ U, int R,
+                                                      const float* U, int R,
                                                       const ShiftArgs sh) {
   rollout_lane_tile<DYN, JUMPS, DEBUG, FORM, FUSED, FULL>(p, b, x0, U, R, sh, blockIdx.x,
                                                          gridDim.x);

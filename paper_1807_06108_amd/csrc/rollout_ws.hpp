@@ -56,6 +56,16 @@ static_assert(WsSplit<MPPI_DYN_CARTPOLE>::first(8) == kWsChunk, "split covers th
 static_assert(WsSplit<MPPI_DYN_QUADROTOR>::first(8) == kWsChunk, "split covers the chunk");
 static_assert(WsSplit<MPPI_DYN_LINEAR>::first(8) == kWsChunk, "split covers the chunk");
 
+// Steps of a full chunk that the consumer's loop unrolls.  Fully unrolled,
+// the 12-state model's chunk has the ring reads of many steps hoisted and
+// spills registers; four steps per trip keep it spill-free and measure
+// fastest for it (K=8192, T=100: 16 steps 52.7 us, 8 steps 52.3, 4 steps
+// 50.7; the same costs and updates bitwise).
+template <int DYN>
+struct WsConsumeUnroll {
+  static constexpr int U = DYN == MPPI_DYN_QUADROTOR ? 4 : kWsChunk;
+};
+
 template <int DYN>
 struct WsRing {
   using Md = Model<DYN>;
@@ -70,7 +80,7 @@ constexpr size_t ws_ring_bytes() {
 
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FULL>
 __device__ __forceinline__ void ws_produce(const DevParams& p, const Consts& cs, const Buffers& b,
-                                           const float* __restrict__ U, float* slot, int t,
+                                           const float* U, float* slot, int t,
                                            int k, bool active, uint32_t it) {
   using Md = Model<DYN>;
   using Rg = WsRing<DYN>;
@@ -156,7 +166,7 @@ __device__ __forceinline__ void ws_consume(const DevParams& p, const Consts& cs,
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, int W, bool FULL = false>
 __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffers& b,
                                                 const float* __restrict__ x0,
-                                                const float* __restrict__ U, int R,
+                                                const float* U, int R,
                                                 const ShiftArgs& sh, int wg, int nwg) {
   using Md = Model<DYN>;
   using Rg = WsRing<DYN>;
@@ -191,35 +201,42 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
   st.S = 0.f;
   st.comp = 0.f;
 
-  for (int c = 0; c <= nch; ++c) {
-    if (wave > 0) {
-      if (c < nch) {
-        float(*buf)[SLOT] = ring[c & 1];
-        if constexpr (W == 8) {
-          for (int s = s0; s < s1; ++s) {
-            const int t = c * kWsChunk + s;
-            if (t < T)
-              ws_produce<DYN, JUMPS, DEBUG, FORM, FULL>(p, cs, b, U, buf[s], t, k, active, it);
-          }
-        } else {
-          for (int s = wave - 1; s < kWsChunk; s += NP) {
-            const int t = c * kWsChunk + s;
-            if (t < T)
-              ws_produce<DYN, JUMPS, DEBUG, FORM, FULL>(p, cs, b, U, buf[s], t, k, active, it);
-          }
+  // Producers and the consumer run separate loops (the branch is uniform per
+  // wavefront), so the register allocation of each holds only its own live
+  // values and constants, not the union of both.  Both loops pass nch + 1
+  // barriers: chunk c is produced before barrier c and consumed after it.
+  if (__builtin_amdgcn_readfirstlane(wave) > 0) {
+    for (int c = 0; c < nch; ++c) {
+      float(*buf)[SLOT] = ring[c & 1];
+      if constexpr (W == 8) {
+        for (int s = s0; s < s1; ++s) {
+          const int t = c * kWsChunk + s;
+          if (t < T)
+            ws_produce<DYN, JUMPS, DEBUG, FORM, FULL>(p, cs, b, U, buf[s], t, k, active, it);
+        }
+      } else {
+        for (int s = wave - 1; s < kWsChunk; s += NP) {
+          const int t = c * kWsChunk + s;
+          if (t < T)
+            ws_produce<DYN, JUMPS, DEBUG, FORM, FULL>(p, cs, b, U, buf[s], t, k, active, it);
         }
       }
-    } else if (c > 0) {
-      const int cc = c - 1;
+      __syncthreads();
+    }
+    __syncthreads();
+  } else {
+    constexpr int kUnroll = WsConsumeUnroll<DYN>::U;
+    __syncthreads();
+    for (int cc = 0; cc < nch; ++cc) {
       float(*buf)[SLOT] = ring[cc & 1];
       if ((cc + 1) * kWsChunk <= T) {
-#pragma unroll
+#pragma unroll kUnroll
         for (int s = 0; s < kWsChunk; ++s) ws_consume<DYN>(p, cs, st, buf[s]);
       } else {
         for (int s = 0; s < T - cc * kWsChunk; ++s) ws_consume<DYN>(p, cs, st, buf[s]);
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
 
   double Sd = 0.0;
@@ -242,7 +259,7 @@ template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL>
 __global__ __launch_bounds__(64 * WsWaves<DYN>::W) void rollout_ws_kernel(const DevParams p,
                                                                          const Buffers b,
                                                                          const float* __restrict__ x0,
-                                                                         const float* __restrict__ U,
+                                                                         const float* U,
                                                                          int R, const ShiftArgs sh) {
   rollout_ws_tile<DYN, JUMPS, DEBUG, FORM, FUSED, WsWaves<DYN>::W, FULL>(p, b, x0, U, R, sh, blockIdx.x,
                                                                    gridDim.x);

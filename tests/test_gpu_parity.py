@@ -239,33 +239,6 @@ def test_partially_nonfinite_costs_are_ignored():
     assert np.abs(ctl.U.cpu().numpy() - ref_U).max() < U_ATOL
 
 
-@pytest.mark.parametrize("preset,K", [("cartpole_mpc", 4096), ("quadrotor_hover", 8192)])
-def test_full_size_sampled_parity(preset, K):
-    """Full benchmark shapes: every S_k checked on a sample of k the oracle
-    computes one by one, plus properties of the whole iteration."""
-    cfg = workloads.PRESETS[preset]()
-    assert cfg["K"] == K
-    x0 = workloads.x0_for(cfg)
-    U0 = workloads.U0_for(cfg, "random")
-    ctl = Controller(cfg, U0)
-    ctl.rollout(x0)
-    S = ctl.S.cpu().numpy()
-    idx = np.unique(np.concatenate([np.arange(0, K, K // 97), [K - 1], np.argsort(S)[:8]]))
-    ref = omppi.iteration(cfg, x0, U0.astype(np.float64), 0, k_index=idx)
-    excl = near_crash(ref)
-    err = s_rel_err(S[idx], ref["S"])[~excl]
-    assert err.max() < S_RTOL, err.max()
-    W = ctl.W.cpu().numpy()
-    assert (W >= 0).all() and abs(W.sum() - 1) < 1e-12
-    st = ctl.stats()
-    assert st["rho"] == S.min() and st["n_finite"] == K
-    eps = ctl.eps.cpu().numpy()
-    ctl.update()
-    dU = ctl.U.cpu().numpy() - U0
-    ref_dU = np.einsum("k,tjk->tj", W, eps.astype(np.float64))
-    assert np.abs(dU - ref_dU).max() < U_ATOL
-
-
 def test_plant_step_matches_the_oracle_dynamics():
     from oracle import models
     for preset in ("cartpole_single", "quadrotor_hover", "double_integrator"):

@@ -394,3 +394,25 @@ class map_pool:
 
     def map(self, fn, jobs):
         return [fn(j) for j in jobs]
+
+
+def test_summed_term_magnitudes():
+    """The scale the GPU tests measure fp32 rounding against: with every term
+    of S~ non-negative (zero nominal sequence, c = 1: no IS term) it is S~
+    itself, bitwise; otherwise it bounds |S~| and exceeds S~ by twice the
+    summed negative parts of the signed IS cross term of eq. (35)."""
+    cfg = workloads.cartpole(K=512, T=40)
+    x0 = workloads.x0_for(cfg)
+    U0 = workloads.U0_for(cfg)
+    z_D, N, z_J = noise.sample(cfg, 0)
+    eps, gust = noise.compose(cfg, z_D, N, z_J)
+    S, _, S_abs = mppi.rollout(cfg, x0, U0, eps, gust, with_magnitude=True)
+    assert np.array_equal(S, S_abs)
+    U = 10.0 * workloads.U0_for(cfg, "random")
+    S, _, S_abs = mppi.rollout(cfg, x0, U, eps, gust, with_magnitude=True)
+    assert (S_abs >= np.abs(S)).all()
+    p = mppi.params(cfg)
+    cross = p["lam"] * (U[None, :, 0] * eps[:, :, 0] * p["inv_var"][0])
+    neg = np.minimum(cross, 0.0).sum(axis=1)
+    assert np.allclose(S_abs - S, -2.0 * neg, rtol=1e-12, atol=1e-9)
+    assert (S_abs > np.abs(S) + 1.0).any()
