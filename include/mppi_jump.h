@@ -192,6 +192,30 @@ int mppi_jump_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, void* s
 int mppi_jump_control_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters,
                            float* d_u0_out, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one MPC
+ * control step exactly as mppi_jump_control_step (same kernels, same
+ * results) without a context or a caller workspace.  The scratch (costs,
+ * perturbations, partials, statistics, counters) lives in a library-owned
+ * static device array of MPPI_JUMP_STATIC_SCRATCH_BYTES per GPU, held until
+ * the process ends; a configuration whose mppi_jump_workspace_bytes exceeds
+ * it is refused with MPPI_EWORKSPACE.  The caller passes cfg (validated as
+ * by mppi_jump_init; debug_dump must be 0, else MPPI_EUNSUPPORTED), the
+ * control sequence d_U ([T][m] fp32 device memory, updated in place and
+ * shifted), the state d_x0 ([n] fp32 device) and d_u0_out ([m] fp32 device,
+ * may be NULL).  Iteration indices (the noise stream position) run from
+ * cfg->start_iteration; a caller continuing a controller passes
+ * start_iteration + iters on its next call.  Nothing is allocated: no
+ * hipMalloc, no hipFree, no host heap.  The first call on a device resolves
+ * the array's device address (hipGetSymbolAddress), so make one call
+ * outside graph capture first.  Every call on one GPU shares that GPU's
+ * array and leaves its contents behind (each call re-initialises what must
+ * start at zero): calls that overlap on one GPU, on different streams or
+ * threads, race and give undefined results. */
+#define MPPI_JUMP_STATIC_SCRATCH_BYTES (16 << 20)
+int mppi_jump_control_step_static(const mppi_jump_config* cfg, float* d_U, const float* d_x0,
+                                  int32_t iters, float* d_u0_out, void* stream);
+
 /* The two halves of one iteration, for callers that stage it:
  * rollout = sampling, propagation and path costs (fills S and eps, and the
  * min / normaliser statistics); update = weights and control update (reads

@@ -729,6 +729,21 @@ __global__ void init_kernel(Buffers b, const float* __restrict__ U0, int R, int 
   }
 }
 
+// Statistics, iteration counter and arrival counters of a workspace reset,
+// leaving U alone (the no-allocation control step, whose sequence belongs
+// to the caller).
+__global__ void stats_init_kernel(Buffers b, uint64_t start_iteration) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    b.stats->rho = 0.0;
+    b.stats->eta = 0.0;
+    b.stats->status = MPPI_OK;
+    b.stats->n_finite = 0;
+    b.stats->iteration = start_iteration;
+    b.counters[0] = 0u;
+    b.counters[1] = 0u;
+  }
+}
+
 // One workgroup of 1024 threads; reads of a chunk finish before its writes.
 __global__ __launch_bounds__(1024) void shift_kernel(float* __restrict__ U, int R, int m,
                                                      float4 u_init) {

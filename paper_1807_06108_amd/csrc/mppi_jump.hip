@@ -12,6 +12,7 @@
 #include <string>
 #include <utility>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "../../include/mppi_jump.h"
@@ -21,20 +22,20 @@ using namespace mppi;
 
 namespace {
 
-thread_local std::string g_last_error;
+// detail of the calling thread's last failure (a fixed buffer: reporting an
+// error allocates nothing)
+thread_local char g_last_error[512];
 
 int fail(int code, const char* fmt, ...) {
-  char buf[512];
   va_list ap;
   va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
+  vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
   va_end(ap);
-  g_last_error = buf;
   return code;
 }
 
 int ok() {
-  g_last_error.clear();
+  g_last_error[0] = '\0';
   return MPPI_OK;
 }
 
@@ -61,12 +62,25 @@ bool dims_of(int32_t dyn, int& n, int& m, int& q) {
   }
 }
 
+// Count-law table of at most MPPI_JUMP_MAX_LEVELS entries, held in place
+// (no heap allocation, so that an entry point can run without allocating).
+struct Thresholds {
+  uint64_t v[MPPI_JUMP_MAX_LEVELS];
+  int n = 0;
+  void clear() { n = 0; }
+  void push_back(uint64_t x) {
+    if (n < MPPI_JUMP_MAX_LEVELS) v[n++] = x;
+  }
+  size_t size() const { return (size_t)n; }
+  uint64_t operator[](size_t i) const { return v[i]; }
+};
+
 // Inversion thresholds of the count law with mean a = nu * dt, computed in
 // fp64: Poisson CDF by the recurrence p_j = p_{j-1} a / j, or the zero-one
 // law F(0) = 1 - a.  theta_j = floor(F(j) 2^32); the first level reaching
 // 2^32 - 1 closes the table at 2^32.  Returns false if the law needs more
 // than MPPI_JUMP_MAX_LEVELS levels.
-bool count_thresholds(double a, int law, std::vector<uint64_t>& th) {
+bool count_thresholds(double a, int law, Thresholds& th) {
   th.clear();
   if (law == MPPI_COUNT_ZERO_ONE) {
     if (a > 1.0) return false;
@@ -94,7 +108,7 @@ bool count_thresholds(double a, int law, std::vector<uint64_t>& th) {
 
 bool finite_pos(float v) { return std::isfinite(v) && v > 0.f; }
 
-int validate(const mppi_jump_config* c, int& n, int& m, int& q, std::vector<uint64_t>& th) {
+int validate(const mppi_jump_config* c, int& n, int& m, int& q, Thresholds& th) {
   if (!c) return fail(MPPI_EINVAL, "config is NULL");
   if (c->abi_version != MPPI_JUMP_ABI_VERSION)
     return fail(MPPI_EINVAL, "abi_version %d != %d", c->abi_version, MPPI_JUMP_ABI_VERSION);
@@ -209,7 +223,7 @@ Layout make_layout(const mppi_jump_config* c, int m, int q) {
 }
 
 DevParams make_params(const mppi_jump_config* c, int n, int m, int q, const Layout& L,
-                      const std::vector<uint64_t>& th) {
+                      const Thresholds& th) {
   DevParams p;
   std::memset(&p, 0, sizeof p);
   p.K = c->K;
@@ -316,6 +330,35 @@ struct mppi_jump_ctx {
 };
 
 namespace {
+
+// Context fields of a validated configuration over a workspace at `base`
+// (laid out by L).
+void bind_context(mppi_jump_ctx* ctx, const mppi_jump_config* cfg, int n, int m, int q,
+                  const Layout& L, const Thresholds& th, char* base) {
+  ctx->cfg = *cfg;
+  ctx->n = n;
+  ctx->m = m;
+  ctx->q = q;
+  ctx->L = L;
+  ctx->p = make_params(cfg, n, m, q, L, th);
+  for (int j = 0; j < MPPI_JUMP_MAX_LEVELS; ++j) ctx->th64[j] = j < (int)th.size() ? th[j] : kTwo32;
+  Buffers& b = ctx->b;
+  b.U = reinterpret_cast<float*>(base + L.U);
+  b.eps = reinterpret_cast<float*>(base + L.eps);
+  b.S = reinterpret_cast<double*>(base + L.S);
+  b.E = reinterpret_cast<double*>(base + L.E);
+  b.part = reinterpret_cast<WgPartial*>(base + L.part);
+  b.scale = reinterpret_cast<double*>(base + L.scale);
+  b.upart = reinterpret_cast<double*>(base + L.upart);
+  b.wpart = L.fused ? reinterpret_cast<double*>(base + L.wpart) : nullptr;
+  b.stats = reinterpret_cast<mppi_jump_stats*>(base + L.stats);
+  b.counters = reinterpret_cast<uint32_t*>(base + L.counters);
+  ctx->W = reinterpret_cast<double*>(base + L.W);
+  b.dbg_zD = cfg->debug_dump ? reinterpret_cast<float*>(base + L.zD) : nullptr;
+  b.dbg_N = cfg->debug_dump ? reinterpret_cast<int32_t*>(base + L.N) : nullptr;
+  b.dbg_zJ = cfg->debug_dump ? reinterpret_cast<float*>(base + L.zJ) : nullptr;
+  ctx->host_iteration = cfg->start_iteration;
+}
 
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL>
 int launch_rollout_t(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, const ShiftArgs& sh) {
@@ -447,7 +490,7 @@ int mppi_jump_workspace_bytes(const mppi_jump_config* cfg, size_t* bytes) {
   return guarded([&]() -> int {
     if (!bytes) return fail(MPPI_EINVAL, "bytes is NULL");
     int n, m, q;
-    std::vector<uint64_t> th;
+    Thresholds th;
     const int rc = validate(cfg, n, m, q, th);
     if (rc != MPPI_OK) return rc;
     *bytes = make_layout(cfg, m, q).total;
@@ -459,7 +502,7 @@ int mppi_jump_count_thresholds(const mppi_jump_config* cfg, uint64_t* out) {
   return guarded([&]() -> int {
     if (!out) return fail(MPPI_EINVAL, "out is NULL");
     int n, m, q;
-    std::vector<uint64_t> th;
+    Thresholds th;
     const int rc = validate(cfg, n, m, q, th);
     if (rc != MPPI_OK) return rc;
     for (int j = 0; j < MPPI_JUMP_MAX_LEVELS; ++j) out[j] = j < (int)th.size() ? th[j] : kTwo32;
@@ -473,7 +516,7 @@ int mppi_jump_init(const mppi_jump_config* cfg, void* d_workspace, size_t ws_byt
     if (!out) return fail(MPPI_EINVAL, "out is NULL");
     *out = nullptr;
     int n, m, q;
-    std::vector<uint64_t> th;
+    Thresholds th;
     int rc = validate(cfg, n, m, q, th);
     if (rc != MPPI_OK) return rc;
     const Layout L = make_layout(cfg, m, q);
@@ -482,30 +525,8 @@ int mppi_jump_init(const mppi_jump_config* cfg, void* d_workspace, size_t ws_byt
     if (ws_bytes < L.total)
       return fail(MPPI_EWORKSPACE, "workspace of %zu bytes < %zu needed", ws_bytes, L.total);
     auto* ctx = new mppi_jump_ctx();
-    ctx->cfg = *cfg;
-    ctx->n = n;
-    ctx->m = m;
-    ctx->q = q;
-    ctx->L = L;
-    ctx->p = make_params(cfg, n, m, q, L, th);
-    for (int j = 0; j < MPPI_JUMP_MAX_LEVELS; ++j) ctx->th64[j] = j < (int)th.size() ? th[j] : kTwo32;
-    char* base = static_cast<char*>(d_workspace);
-    Buffers& b = ctx->b;
-    b.U = reinterpret_cast<float*>(base + L.U);
-    b.eps = reinterpret_cast<float*>(base + L.eps);
-    b.S = reinterpret_cast<double*>(base + L.S);
-    b.E = reinterpret_cast<double*>(base + L.E);
-    b.part = reinterpret_cast<WgPartial*>(base + L.part);
-    b.scale = reinterpret_cast<double*>(base + L.scale);
-    b.upart = reinterpret_cast<double*>(base + L.upart);
-    b.wpart = L.fused ? reinterpret_cast<double*>(base + L.wpart) : nullptr;
-    b.stats = reinterpret_cast<mppi_jump_stats*>(base + L.stats);
-    b.counters = reinterpret_cast<uint32_t*>(base + L.counters);
-    ctx->W = reinterpret_cast<double*>(base + L.W);
-    b.dbg_zD = cfg->debug_dump ? reinterpret_cast<float*>(base + L.zD) : nullptr;
-    b.dbg_N = cfg->debug_dump ? reinterpret_cast<int32_t*>(base + L.N) : nullptr;
-    b.dbg_zJ = cfg->debug_dump ? reinterpret_cast<float*>(base + L.zJ) : nullptr;
-    ctx->host_iteration = cfg->start_iteration;
+    bind_context(ctx, cfg, n, m, q, L, th, static_cast<char*>(d_workspace));
+    const Buffers& b = ctx->b;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const int threads = 256, blocks = (L.R + threads - 1) / threads;
     init_kernel<<<blocks, threads, 0, s>>>(b, d_U0, L.R, m, u_init4(*cfg), cfg->start_iteration);
@@ -567,6 +588,68 @@ int mppi_jump_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, void* s
   });
 }
 
+}  // extern "C"
+
+namespace {
+
+// Body of mppi_jump_control_step on a checked context.
+int enqueue_control_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, float* d_u0_out,
+                         void* stream) {
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!ctx->L.fused) {
+    int rc = mppi_jump_step(ctx, d_x0, iters, stream);
+    if (rc != MPPI_OK) return rc;
+    return mppi_jump_shift(ctx, d_u0_out, stream);
+  }
+  int rc = bracket_begin(ctx, s);
+  if (rc != MPPI_OK) return rc;
+  for (int i = 0; i < iters; ++i) {
+    ShiftArgs sh{};
+    if (i == iters - 1) {
+      sh.on = 1;
+      sh.u0_out = d_u0_out;
+      sh.m = ctx->m;
+      sh.u_init = u_init4(ctx->cfg);
+    }
+    rc = launch_rollout(ctx, d_x0, s, true, sh, false);
+    if (rc != MPPI_OK) return rc;
+    ctx->host_iteration += 1;
+  }
+  rc = bracket_end(ctx, s, iters);
+  return rc == MPPI_OK ? ok() : rc;
+}
+
+// Scratch of mppi_jump_control_step_static: a library-owned device array,
+// one copy per GPU, held until the process ends.  In host code its name
+// stands for the host-side shadow, not a device address: the device address
+// is resolved once per device by hipGetSymbolAddress and only that address
+// is used.
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[MPPI_JUMP_STATIC_SCRATCH_BYTES];
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (resolved on the first
+// call per device, with that device current).
+int static_scratch(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(MPPI_EDEVICE, "device %d beyond %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || ((uintptr_t)p & 255u)) return fail(MPPI_EDEVICE, "static scratch address unusable");
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return MPPI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int mppi_jump_control_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, float* d_u0_out,
                            void* stream) {
   return guarded([&]() -> int {
@@ -574,28 +657,40 @@ int mppi_jump_control_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters,
     if (iters < 1) return fail(MPPI_EINVAL, "iters=%d < 1", iters);
     if (ctx->host_iteration + (uint64_t)iters > kTwo32)
       return fail(MPPI_EINVAL, "iteration counter would pass 2^32");
-    const hipStream_t s = static_cast<hipStream_t>(stream);
-    if (!ctx->L.fused) {
-      int rc = mppi_jump_step(ctx, d_x0, iters, stream);
-      if (rc != MPPI_OK) return rc;
-      return mppi_jump_shift(ctx, d_u0_out, stream);
-    }
-    int rc = bracket_begin(ctx, s);
+    return enqueue_control_step(ctx, d_x0, iters, d_u0_out, stream);
+  });
+}
+
+int mppi_jump_control_step_static(const mppi_jump_config* cfg, float* d_U, const float* d_x0,
+                                  int32_t iters, float* d_u0_out, void* stream) {
+  return guarded([&]() -> int {
+    if (!d_U || !d_x0) return fail(MPPI_EINVAL, "NULL control sequence or state");
+    if (iters < 1) return fail(MPPI_EINVAL, "iters=%d < 1", iters);
+    int n, m, q;
+    Thresholds th;
+    int rc = validate(cfg, n, m, q, th);
     if (rc != MPPI_OK) return rc;
-    for (int i = 0; i < iters; ++i) {
-      ShiftArgs sh{};
-      if (i == iters - 1) {
-        sh.on = 1;
-        sh.u0_out = d_u0_out;
-        sh.m = ctx->m;
-        sh.u_init = u_init4(ctx->cfg);
-      }
-      rc = launch_rollout(ctx, d_x0, s, true, sh, false);
-      if (rc != MPPI_OK) return rc;
-      ctx->host_iteration += 1;
-    }
-    rc = bracket_end(ctx, s, iters);
-    return rc == MPPI_OK ? ok() : rc;
+    if (cfg->debug_dump) return fail(MPPI_EUNSUPPORTED, "debug_dump needs a context and its workspace");
+    if (cfg->start_iteration + (uint64_t)iters > kTwo32)
+      return fail(MPPI_EINVAL, "iteration counter would pass 2^32");
+    const Layout L = make_layout(cfg, m, q);
+    if (L.total > (size_t)MPPI_JUMP_STATIC_SCRATCH_BYTES)
+      return fail(MPPI_EWORKSPACE, "K=%d, T=%d needs %zu bytes of scratch, above the static "
+                  "maximum of %zu", cfg->K, cfg->T, L.total, (size_t)MPPI_JUMP_STATIC_SCRATCH_BYTES);
+    void* base = nullptr;
+    rc = static_scratch(&base);
+    if (rc != MPPI_OK) return rc;
+    // a context on the stack over the static scratch; the sequence is the
+    // caller's (its region of the layout stays unused)
+    mppi_jump_ctx ctx;
+    bind_context(&ctx, cfg, n, m, q, L, th, static_cast<char*>(base));
+    ctx.b.U = d_U;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    // statistics, iteration counter and arrival counters start afresh (a fill
+    // kernel, not a memset node, so that the call can be captured)
+    stats_init_kernel<<<1, 64, 0, s>>>(ctx.b, cfg->start_iteration);
+    LAUNCH_CHECK("stats_init_kernel");
+    return enqueue_control_step(&ctx, d_x0, iters, d_u0_out, stream);
   });
 }
 
@@ -1172,7 +1267,7 @@ const char* mppi_jump_strerror(int code) {
   }
 }
 
-const char* mppi_jump_last_error(void) { return g_last_error.c_str(); }
+const char* mppi_jump_last_error(void) { return g_last_error; }
 
 int mppi_jump_plant_step(mppi_jump_ctx* ctx, float* d_x, const float* d_u, const float* d_dist,
                          void* stream) {

@@ -106,6 +106,9 @@ _PROTOS = {
     "mppi_jump_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "mppi_jump_control_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                               ctypes.c_void_p, ctypes.c_void_p]),
+    "mppi_jump_control_step_static": (ctypes.c_int, [ctypes.POINTER(Config), ctypes.c_void_p,
+                                                     ctypes.c_void_p, ctypes.c_int32,
+                                                     ctypes.c_void_p, ctypes.c_void_p]),
     "mppi_jump_rollout": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "mppi_jump_update": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "mppi_jump_shift": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
