@@ -23,11 +23,16 @@ The JSON line also carries
                    MPC-step requests/s: p50/p99 latency (arrival to u0 on the
                    host) of pooled ticks against per-controller launches, and
                    the capacity of each back end,
+  other_configs    the other single-GPU configurations, each with its value,
+                   time per iteration, roofline and oracle timings: the single
+                   cartpole iteration (K=256, T=50) and the quadrotor hover
+                   iteration (K=8192, T=100),
   cpu_baseline     the FP64 oracle on a bounded sample of the same loop, one
-                   thread,
+                   thread, with the host's processor, nproc and usable cores,
   cpu_baseline_all_cores
                    the same with each iteration's samples split over the host
-                   cores (worker processes).
+                   cores (worker processes, at most 16: the host CPU share of
+                   one GPU on the measurement machines).
 """
 
 import argparse
@@ -111,14 +116,22 @@ def cpu_baseline(cfg, x0, U0, iters, dist, budget_s):
     el = time.perf_counter() - t0
     return dict(value=cfg["K"] * cfg["T"] * iters * steps / el, unit="rollout-steps/s",
                 ms_per_control_step=1e3 * el / steps,
-                cores=1, kind="oracle", cpu=host_cpu(),
+                cores=1, kind="oracle", **host_info(),
                 sample="%d closed-loop control steps of this workload (%d iterations each, "
                        "K=%d, T=%d), %.1f s, single thread" % (steps, iters, cfg["K"],
                                                                cfg["T"], el))
 
 
 def host_cpu():
-    """Model name of the host processor (first entry of /proc/cpuinfo)."""
+    """Model name of the host processor (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
@@ -129,50 +142,136 @@ def host_cpu():
     return "unknown"
 
 
-def cpu_baseline_all_cores(cfg, x0, U0, iters, dist, budget_s, workers):
-    """The same oracle with each iteration's samples split over `workers`
-    processes (oracle.shards: the parent forms the weights and update;
-    results equal the one-thread oracle).  Workers start from a fresh
-    interpreter (no GPU state) with one BLAS thread each; their start-up is
-    not timed.  A worker that dies raises (BrokenProcessPool) instead of
-    being replaced."""
-    import multiprocessing as mp
-    from concurrent.futures import ProcessPoolExecutor
-    from oracle import models, shards
+def host_info():
+    """The host's processor, its logical CPU count (nproc) and the cores this
+    process may use (its affinity set)."""
+    return {"cpu": host_cpu(), "nproc": os.cpu_count(),
+            "usable_cores": len(os.sched_getaffinity(0))}
+
+
+# Worker processes of the all-cores oracle timing: the usable cores, at most
+# 16, the host CPU share of one GPU on the measurement machines (their nproc
+# is larger; host_info reports it).
+MAX_CPU_WORKERS = 16
+
+
+def cpu_iterations(cfg, x0, U0, budget_s, pool=None, workers=1):
+    """The oracle on a bounded sample of a single-iteration workload:
+    iterations from the same state with fresh iteration indices, each from
+    the previous one's sequence, until budget_s has passed; on one thread, or
+    with each iteration's samples split over `workers` processes of `pool`."""
     from oracle import mppi as omppi
-    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
-    saved = {k: os.environ.get(k) for k in keys}
+    from oracle import shards
     x = x0.astype(np.float64)
     U = U0.astype(np.float64)
-    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as pool:
-        for k in keys:
-            os.environ[k] = "1"
-        try:
-            shards.iteration_U(pool, workers, cfg, x, U, 0)  # starts the workers
-        finally:
-            for k, v in saved.items():
-                if v is None:
-                    os.environ.pop(k, None)
-                else:
-                    os.environ[k] = v
-        P = omppi.f32(cfg["params"])
-        dt = float(omppi.f32(cfg["dt"]))
-        t0 = time.perf_counter()
-        steps = 0
-        while True:
-            u0, U = shards.control_step(pool, workers, cfg, x, U, steps * iters, iters)
-            x = models.euler_step(cfg["dynamics"], x[None], (u0 + dist[steps])[None],
-                                  np.zeros((1, 3)), dt, P)[0]
-            steps += 1
-            if time.perf_counter() - t0 > budget_s or steps >= len(dist):
-                break
-        el = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        if pool is None:
+            U = omppi.iteration(cfg, x, U, n)["U"]
+        else:
+            U = shards.iteration_U(pool, workers, cfg, x, U, n)
+        n += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    return dict(value=cfg["K"] * cfg["T"] * n / el, unit="rollout-steps/s",
+                ms_per_iteration=1e3 * el / n, cores=workers, kind="oracle",
+                sample="%d iterations (K=%d, T=%d), %.1f s, %s" % (
+                    n, cfg["K"], cfg["T"], el,
+                    "single thread" if pool is None else
+                    "samples split over %d worker processes" % workers),
+                **host_info())
+
+
+def oracle_pool(workers):
+    """A pool of `workers` fresh interpreter processes with one BLAS thread
+    each (started and warmed up outside any timed region)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in keys}
+    for k in keys:
+        os.environ[k] = "1"
+    try:
+        pool = ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"))
+        list(pool.map(abs, range(workers)))  # start every worker
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    return pool
+
+
+def cpu_baseline_all_cores(cfg, x0, U0, iters, dist, budget_s, pool, workers):
+    """The same oracle with each iteration's samples split over the `workers`
+    processes of `pool` (oracle.shards: the parent forms the weights and
+    update; results equal the one-thread oracle).  A worker that dies raises
+    (BrokenProcessPool) instead of being replaced."""
+    from oracle import models, shards
+    from oracle import mppi as omppi
+    x = x0.astype(np.float64)
+    U = U0.astype(np.float64)
+    P = omppi.f32(cfg["params"])
+    dt = float(omppi.f32(cfg["dt"]))
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        u0, U = shards.control_step(pool, workers, cfg, x, U, steps * iters, iters)
+        x = models.euler_step(cfg["dynamics"], x[None], (u0 + dist[steps])[None],
+                              np.zeros((1, 3)), dt, P)[0]
+        steps += 1
+        if time.perf_counter() - t0 > budget_s or steps >= len(dist):
+            break
+    el = time.perf_counter() - t0
     return dict(value=cfg["K"] * cfg["T"] * iters * steps / el, unit="rollout-steps/s",
                 ms_per_control_step=1e3 * el / steps,
-                cores=workers, kind="oracle", cpu=host_cpu(),
+                cores=workers, kind="oracle", **host_info(),
                 sample="%d closed-loop control steps of this workload, each iteration's "
                        "K=%d samples split over %d worker processes, %.1f s"
                        % (steps, cfg["K"], workers, el))
+
+
+def iteration_measure(name, calls, warmup):
+    """One plain-form controller of a preset single-iteration workload: `calls`
+    iterations (one fused launch each, the rollout kernel timed by HIP events
+    on its stream around every launch) from the preset state, each from the
+    previous one's sequence.  Returns the workload's sub-object of the line
+    (its cpu_baseline legs are added by the caller)."""
+    import torch
+    from paper_1807_06108_amd import workloads
+    from paper_1807_06108_amd.controller import Controller
+    cfg = workloads.PRESETS[name]()
+    K, T, dyn = cfg["K"], cfg["T"], cfg["dynamics"]
+    ctl = Controller(cfg, workloads.U0_for(cfg))
+    x = torch.tensor(workloads.x0_for(cfg), device="cuda")
+    for _ in range(warmup):
+        ctl.step(x, 1)
+    torch.cuda.synchronize()
+    ctl.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        ctl.step(x, 1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctl.profile(False)
+    roll_ms, launches = ctl.profile_read()
+    avg_roll_s = roll_ms / launches * 1e-3
+    achieved = ALG_SLOTS[dyn] * K * T / avg_roll_s
+    flops = ALG_FP32_FLOP[dyn] * K * T / avg_roll_s
+    return {"workload": name, "K": K, "T": T, "dt": cfg["dt"], "dynamics": dyn, "nu": cfg["nu"],
+            "iterations": calls, "value": K * T * calls / wall, "unit": "rollout-steps/s",
+            "ms_per_iteration": wall / calls * 1e3,
+            "roofline": {"bound": "alu",
+                         "kernel": "rollout (sampling, propagation, cost, weights, update)",
+                         "achieved": achieved / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
+                         "unit": "T VALU-slot/s", "frac": achieved / VALU_PEAK_SLOTS,
+                         "traffic": measured_traffic(name),
+                         "avg_launch_us": avg_roll_s * 1e6, "launches_timed": launches,
+                         "slots_per_sample_step": ALG_SLOTS[dyn],
+                         "fp32_tflops": flops / 1e12, "fp32_frac": flops / FP32_PEAK}}
 
 
 def batched_measure(n_ctl, ticks, warmup, seed=42):
@@ -284,6 +383,56 @@ def serving_measure(rate, seconds, warm, n_ctl=1024, seed=4):
     return out
 
 
+def counter_per_dispatch(csv_dir, counter, kernel_prefix):
+    """(mean value per dispatch, dispatches) of one rocprofv3 counter over
+    the dispatches of kernels whose name starts with kernel_prefix, from the
+    *counter_collection.csv files under csv_dir."""
+    import csv
+    import glob
+    vals = {}
+    for path in glob.glob(os.path.join(csv_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                name = row.get("Kernel_Name", "")
+                if row.get("Counter_Name") != counter or not name.startswith(kernel_prefix):
+                    continue
+                key = (path, row.get("Dispatch_Id"))
+                vals[key] = vals.get(key, 0.0) + float(row["Counter_Value"])
+    if not vals:
+        raise ValueError("no %s dispatches of %s under %s" % (counter, kernel_prefix, csv_dir))
+    return sum(vals.values()) / len(vals), len(vals)
+
+
+def traffic_summary(pmc_dir, workloads):
+    """HBM bytes per rollout launch from FETCH_SIZE and WRITE_SIZE runs (KiB
+    per dispatch), each scaled by what the same counter reads for the copy
+    of known size (bench.py --calibrate-copy).  Expects pmc_dir/<counter>_copy
+    and pmc_dir/<counter>_<workload> for both counters."""
+    copy_bytes = 256 << 20
+    # the copy dispatches of calibrate_copy (its fill kernel excluded)
+    copy_kernel = "__amd_rocclr_copyBuffer"
+    cf, _ = counter_per_dispatch(os.path.join(pmc_dir, "FETCH_SIZE_copy"), "FETCH_SIZE",
+                                 copy_kernel)
+    cw, _ = counter_per_dispatch(os.path.join(pmc_dir, "WRITE_SIZE_copy"), "WRITE_SIZE",
+                                 copy_kernel)
+    fetch_scale, write_scale = copy_bytes / (cf * 1024), copy_bytes / (cw * 1024)
+    out = {"source_hash": source_hash(),
+           "what": "HBM bytes per launch of the rollout kernel: rocprofv3 FETCH_SIZE and "
+                   "WRITE_SIZE (KiB per dispatch), each scaled by the reading of the same "
+                   "counter for a 256 MiB device-to-device copy",
+           "copy_calibration": {"bytes": copy_bytes, "FETCH_SIZE_kib": cf, "WRITE_SIZE_kib": cw,
+                                "fetch_scale": fetch_scale, "write_scale": write_scale},
+           "workloads": {}}
+    for w in workloads:
+        f, nf = counter_per_dispatch(os.path.join(pmc_dir, "FETCH_SIZE_" + w), "FETCH_SIZE",
+                                     "void mppi::rollout")
+        wr, nw = counter_per_dispatch(os.path.join(pmc_dir, "WRITE_SIZE_" + w), "WRITE_SIZE",
+                                      "void mppi::rollout")
+        out["workloads"][w] = {"FETCH_SIZE_kib": f, "WRITE_SIZE_kib": wr, "dispatches": [nf, nw],
+                               "bytes_per_launch": 1024 * (f * fetch_scale + wr * write_scale)}
+    return out
+
+
 def calibrate_copy(nbytes=256 << 20, reps=4):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -310,11 +459,17 @@ def main():
                     help="rollout schedule (identical results)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--iteration-calls", type=int, default=300,
+                    help="iterations timed on each other single-GPU configuration "
+                         "(cartpole K=256 T=50, quadrotor K=8192 T=100); 0 skips them")
     ap.add_argument("--cpu-workers", type=int, default=None,
                     help="worker processes of the all-cores oracle timing (default: the "
                          "usable host cores, at most 16; 0 skips it)")
     ap.add_argument("--host-loop-steps", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--traffic-summary", metavar="PMC_DIR",
+                    help="print the HBM bytes per rollout launch from the FETCH_SIZE / "
+                         "WRITE_SIZE counter runs under PMC_DIR (no GPU needed)")
     ap.add_argument("--batched-controllers", type=int, default=256)
     ap.add_argument("--batched-ticks", type=int, default=20,
                     help="0 skips the batched-form comparison")
@@ -323,6 +478,11 @@ def main():
     ap.add_argument("--serving-warmup", type=float, default=2.0)
     ap.add_argument("--serving-rate", type=float, default=20000.0)
     args = ap.parse_args()
+    if args.traffic_summary:
+        print(json.dumps(traffic_summary(args.traffic_summary,
+                                         ("cartpole_mpc", "cartpole_single", "quadrotor_hover")),
+                         indent=1))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the method's parallel axis (samples) fits one "
               "MI355X and no multi-GPU path is built; run with --gpus 1", file=sys.stderr)
@@ -446,22 +606,51 @@ def main():
         progress("serving form (about %.0f s)" % (2 * (args.serving_seconds + args.serving_warmup) + 5))
         line["serving"] = serving_measure(args.serving_rate, args.serving_seconds,
                                           args.serving_warmup)
+    # the other single-GPU configurations: the single cartpole iteration
+    # (K=256, T=50) and the quadrotor hover iteration (K=8192, T=100)
+    others = []
+    if args.iteration_calls > 0 and args.K is None and args.T is None:
+        for name in ("cartpole_single", "quadrotor_hover"):
+            if name != args.workload:
+                progress("plain form: %s" % name)
+                others.append(iteration_measure(name, args.iteration_calls, 20))
+        line["other_configs"] = others
     if not args.no_cpu_baseline:
-        progress("oracle on the host cores (about %.0f s)" % args.cpu_budget)
+        progress("oracle on one host core (about %.0f s)" % args.cpu_budget)
         line["cpu_baseline"] = cpu_baseline(cfg, x0, U0, iters,
                                             dist[args.warmup:].astype(np.float64),
                                             args.cpu_budget)
+        from paper_1807_06108_amd import workloads as wl
+        for o in others:
+            c = wl.PRESETS[o["workload"]]()
+            progress("oracle on one host core: %s (about %.0f s)" % (o["workload"],
+                                                                    args.cpu_budget / 2))
+            o["cpu_baseline"] = cpu_iterations(c, wl.x0_for(c), wl.U0_for(c),
+                                               args.cpu_budget / 2)
         workers = args.cpu_workers
         if workers is None:
-            workers = min(16, len(os.sched_getaffinity(0)))
+            workers = min(MAX_CPU_WORKERS, len(os.sched_getaffinity(0)))
         if workers > 1:
-            progress("oracle on %d host cores (about %.0f s)" % (workers, args.cpu_budget / 2))
             try:
-                line["cpu_baseline_all_cores"] = cpu_baseline_all_cores(
-                    cfg, x0, U0, iters, dist[args.warmup:].astype(np.float64),
-                    args.cpu_budget / 2, workers)
+                pool = oracle_pool(workers)
             except Exception as e:  # the GPU figures stand without it
+                pool = None
                 line["cpu_baseline_all_cores"] = {"error": repr(e)}
+            if pool is not None:
+                with pool:
+                    progress("oracle on %d host cores (about %.0f s)" % (workers,
+                                                                         args.cpu_budget / 2))
+                    try:
+                        line["cpu_baseline_all_cores"] = cpu_baseline_all_cores(
+                            cfg, x0, U0, iters, dist[args.warmup:].astype(np.float64),
+                            args.cpu_budget / 2, pool, workers)
+                        for o in others:
+                            c = wl.PRESETS[o["workload"]]()
+                            progress("oracle on %d host cores: %s" % (workers, o["workload"]))
+                            o["cpu_baseline_all_cores"] = cpu_iterations(
+                                c, wl.x0_for(c), wl.U0_for(c), args.cpu_budget / 3, pool, workers)
+                    except Exception as e:
+                        line["cpu_baseline_all_cores"] = {"error": repr(e)}
     print(json.dumps(line), flush=True)
 
 

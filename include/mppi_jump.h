@@ -72,7 +72,7 @@ extern "C" {
 
 /* rollout schedules (identical results, different parallel decomposition):
  * one sample per lane, 256 samples per workgroup; or wave-specialised, 64
- * samples per workgroup of 4 wavefronts (3 draw noise, 1 runs the state
+ * samples per workgroup of 8 wavefronts (7 draw noise, 1 runs the state
  * recursion), for latency when K does not fill the GPU.  AUTO picks
  * wave-specialised for K <= MPPI_JUMP_WS_MAX_K. */
 #define MPPI_SCHED_AUTO 0
@@ -85,7 +85,7 @@ extern "C" {
 #define MPPI_ITEM_S 1        /* double [K] path costs S~_k          get, set */
 #define MPPI_ITEM_W 2        /* double [K] normalised weights       get      */
 #define MPPI_ITEM_STATS 3    /* mppi_jump_stats                     get      */
-#define MPPI_ITEM_EPS 4      /* float [T][m][K] perturbations       get      */
+#define MPPI_ITEM_EPS 4      /* float [T][m][K] perturbations       get; see below */
 #define MPPI_ITEM_DBG_ZD 5   /* float [K][T][m] standard normals z_D  (debug_dump) */
 #define MPPI_ITEM_DBG_N 6    /* int32 [K][T] jump counts              (debug_dump) */
 #define MPPI_ITEM_DBG_ZJ 7   /* float [K][T][q] standard normals z_J  (debug_dump) */
@@ -232,7 +232,14 @@ int mppi_jump_shift(mppi_jump_ctx* ctx, float* u0_out, void* stream);
 
 /* Enqueue a copy of an item (MPPI_ITEM_*) into dst (device or host memory).
  * EINVAL if dst_bytes is smaller than the item; EUNSUPPORTED for a debug
- * item of a context created without debug_dump.  MPPI_ITEM_W and
+ * item of a context created without debug_dump, and for MPPI_ITEM_EPS after
+ * an iteration that kept its perturbations on chip: the fused
+ * wave-specialised iteration (mppi_jump_step / mppi_jump_control_step with
+ * at most 512 rollout workgroups) holds its tile of perturbations in LDS
+ * until the update has used them and never stores them, when the tile fits
+ * (the one-channel models with T <= 496; the quadrotor stores its tile);
+ * every staged rollout (mppi_jump_rollout), unfused or lane-schedule
+ * iteration, batch step and pool tick stores them.  MPPI_ITEM_W and
  * MPPI_ITEM_THRESH are computed at call time (W from the current S and
  * statistics).  A host dst is complete only after the stream is synchronised. */
 int mppi_jump_get(mppi_jump_ctx* ctx, int32_t what, void* dst, size_t dst_bytes, void* stream);

@@ -139,10 +139,13 @@ __device__ __forceinline__ void acquire_fence() { __builtin_amdgcn_fence(__ATOMI
 // arrival counter is incremented (a device-scope release writes back the L2
 // of this XCD, so one per workgroup instead of one per wavefront).
 // wg / nwg: this workgroup's index among the nwg workgroups of its controller.
+// tile / tstride (FUSED): the workgroup's perturbations, row r (= t m + j)
+// of its SPW samples at tile[r tstride ..] (on chip, or its columns of the
+// HBM array).
 template <int SPW, bool FUSED, int NT = kBlock>
 __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffers& b, double Sd,
                                                  bool active, int R, const ShiftArgs sh, int wg,
-                                                 int nwg) {
+                                                 int nwg, const float* tile, int tstride) {
   constexpr int NW = NT / 64;
   constexpr int RPP = NT / 4;  // eps tile rows per pass, four threads per row
   __shared__ double lds[NW];
@@ -191,7 +194,7 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
         double acc = 0.0;
         if (i < nrow) {
           const float4* row =
-              reinterpret_cast<const float4*>(b.eps + (size_t)(base + i) * p.Ks + k0 + q * SQ);
+              reinterpret_cast<const float4*>(tile + (size_t)(base + i) * tstride + q * SQ);
           const double* ew = e_lds + q * SQ;
 #pragma unroll
           for (int j = 0; j < SQ / 4; ++j) {
@@ -638,7 +641,8 @@ __device__ __forceinline__ void rollout_lane_tile(const DevParams& p, const Buff
   kahan_add(S, comp, qf);
   const double Sd = (double)S - (double)comp;
   if (active) b.S[k] = Sd;
-  rollout_epilogue<kBlock, FUSED>(p, b, Sd, active, R, sh, wg, nwg);
+  rollout_epilogue<kBlock, FUSED>(p, b, Sd, active, R, sh, wg, nwg,
+                                  b.eps + (size_t)wg * kBlock, p.Ks);
 }
 
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL>
@@ -657,7 +661,8 @@ __global__ __launch_bounds__(256) void restats_kernel(const DevParams p, const B
   const int k = blockIdx.x * SPW + threadIdx.x;
   const bool active = threadIdx.x < SPW && k < p.K;
   const double Sd = active ? b.S[k] : 0.0;
-  rollout_epilogue<SPW, false>(p, b, Sd, active, 0, ShiftArgs{}, blockIdx.x, gridDim.x);
+  rollout_epilogue<SPW, false>(p, b, Sd, active, 0, ShiftArgs{}, blockIdx.x, gridDim.x, nullptr,
+                               0);
 }
 
 // ------------------------------------------------------------------ update

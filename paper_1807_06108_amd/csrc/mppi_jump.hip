@@ -179,6 +179,7 @@ struct Layout {
   bool ws;     // wave-specialised schedule (64 samples per workgroup)
   int spw;     // samples per rollout workgroup
   bool fused;
+  bool eps_lds;  // fused wave-specialised iterations keep the perturbations on chip
   size_t U, eps, S, E, part, scale, upart, wpart, stats, counters, W, zD, N, zJ, total;
 };
 
@@ -209,6 +210,13 @@ Layout make_layout(const mppi_jump_config* c, int m, int q) {
   L.scale = take((size_t)L.nwg * 8);
   L.upart = take((size_t)L.R * L.nch * 8);
   L.fused = L.nwg <= kFusedMaxWg;
+  bool fits = false;
+  switch (c->dynamics) {
+    case MPPI_DYN_LINEAR: fits = ws_eps_fits<MPPI_DYN_LINEAR>(L.R); break;
+    case MPPI_DYN_CARTPOLE: fits = ws_eps_fits<MPPI_DYN_CARTPOLE>(L.R); break;
+    default: fits = ws_eps_fits<MPPI_DYN_QUADROTOR>(L.R); break;
+  }
+  L.eps_lds = L.ws && L.fused && !c->debug_dump && fits;
   L.wpart = take(L.fused ? (size_t)L.nwg * L.R * 8 : 0);
   L.stats = take(sizeof(mppi_jump_stats));
   L.counters = take(2 * sizeof(uint32_t));
@@ -320,6 +328,7 @@ struct mppi_jump_ctx {
   double* W;
   uint64_t th64[MPPI_JUMP_MAX_LEVELS];
   uint64_t host_iteration;  // iterations enqueued so far (range check only)
+  bool eps_stored = true;   // the last rollout enqueued stored its perturbations
   bool profiling = false;
   struct Bracket {
     hipEvent_t e0, e1;
@@ -360,10 +369,33 @@ void bind_context(mppi_jump_ctx* ctx, const mppi_jump_config* cfg, int n, int m,
   ctx->host_iteration = cfg->start_iteration;
 }
 
+// The fused wave-specialised kernel with its perturbation tile on chip (the
+// one-channel models): its dynamic LDS (ring plus tile) can exceed the
+// default launch limit, so the kernel's limit is raised once, to the compute
+// unit's LDS less the static part bounded by kWsStaticLds.
+template <int DYN, bool JUMPS, int FORM, bool FULL>
+int launch_ws_eps_lds(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, const ShiftArgs& sh) {
+  const auto kern = rollout_ws_kernel<DYN, JUMPS, false, FORM, true, FULL, true>;
+  static const hipError_t raised = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+      (int)(kLdsBytes - kWsStaticLds));
+  if (raised != hipSuccess)
+    return fail(MPPI_EDEVICE, "raising the LDS limit of rollout_ws_kernel: %s",
+                hipGetErrorString(raised));
+  kern<<<dim3(ctx->L.nwg), dim3(64 * WsWaves<DYN>::W), ws_eps_lds_bytes<DYN>(ctx->L.R), s>>>(
+      ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R, sh);
+  LAUNCH_CHECK("rollout_ws_kernel");
+  return MPPI_OK;
+}
+
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL>
 int launch_rollout_t(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, const ShiftArgs& sh) {
+  ctx->eps_stored = !(FUSED && !DEBUG && ctx->L.eps_lds);
+  if constexpr (FUSED && !DEBUG && Model<DYN>::M == 1) {  // one-channel models only
+    if (ctx->L.eps_lds) return launch_ws_eps_lds<DYN, JUMPS, FORM, FULL>(ctx, x0, s, sh);
+  }
   if (ctx->L.ws) {
-    rollout_ws_kernel<DYN, JUMPS, DEBUG, FORM, FUSED, FULL>
+    rollout_ws_kernel<DYN, JUMPS, DEBUG, FORM, FUSED, FULL, false>
         <<<dim3(ctx->L.nwg), dim3(64 * WsWaves<DYN>::W), ws_ring_bytes<DYN>(), s>>>(
             ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R, sh);
     LAUNCH_CHECK("rollout_ws_kernel");
@@ -730,6 +762,9 @@ int mppi_jump_get(mppi_jump_ctx* ctx, int32_t what, void* dst, size_t dst_bytes,
         break;
       }
       case MPPI_ITEM_EPS: {
+        if (!ctx->eps_stored)
+          return fail(MPPI_EUNSUPPORTED, "the last iteration kept its perturbations on chip "
+                      "(fused wave-specialised form); a staged rollout stores them");
         if (need((size_t)ctx->L.R * K * 4) != MPPI_OK) return MPPI_EINVAL;
         HIP_TRY(hipMemcpy2DAsync(dst, K * 4, ctx->b.eps, (size_t)ctx->L.Ks * 4, K * 4,
                                  (size_t)ctx->L.R, hipMemcpyDefault, s));
@@ -942,7 +977,10 @@ int mppi_jump_batch_step(mppi_jump_batch* bt, int32_t iters, int32_t shift, void
         batch_rollout_kernel<false><<<grid, block, 0, s>>>(bt->d_desc, bt->d_tiles, sh);
       LAUNCH_CHECK("batch_rollout_kernel");
     }
-    for (auto* c : bt->ctxs) c->host_iteration += (uint64_t)iters;
+    for (auto* c : bt->ctxs) {
+      c->host_iteration += (uint64_t)iters;
+      c->eps_stored = true;  // batched tiles store their perturbations
+    }
     return ok();
   });
 }
@@ -1191,6 +1229,7 @@ int mppi_jump_pool_tick(mppi_jump_pool* pl, const int32_t* ids, const float* sta
     for (int i = 0; i < count; ++i) {
       pl->busy[ids[i]] = slot;
       pl->ctxs[ids[i]]->host_iteration += (uint64_t)iters;
+      pl->ctxs[ids[i]]->eps_stored = true;  // pooled tiles store their perturbations
     }
     return ok();
   });

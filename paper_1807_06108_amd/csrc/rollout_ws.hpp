@@ -35,13 +35,13 @@ struct WsWaves {
 // draw blocks per step keep the producers close to the consumer's pace, and
 // its mate keeps an even share (two steps: the per-wave counts of a
 // round-robin split; one step measures the same, three are slower).
-template <int DYN>
+template <int DYN, int CH = kWsChunk>
 struct WsSplit {
   static constexpr int MATE = DYN == MPPI_DYN_QUADROTOR ? 2 : 1;
   __host__ __device__ static constexpr int count(int w) {
     if (w <= 0 || w > 7) return 0;
     if (w == 4) return MATE;
-    const int rem = kWsChunk - MATE;
+    const int rem = CH - MATE;
     const int simd = w & 3;  // 1..3
     const int n = rem / 3 + (simd - 1 < rem % 3 ? 1 : 0);
     return w < 4 ? (n + 1) / 2 : n / 2;
@@ -78,9 +78,32 @@ constexpr size_t ws_ring_bytes() {
   return sizeof(float) * 2 * kWsChunk * WsRing<DYN>::NF * 64;
 }
 
-template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FULL>
+// On-chip perturbation tile of the fused wave-specialised rollout
+// (EPS_LDS): the workgroup's eps[t][j][k] for its 64 samples, R = T m rows
+// of 64 floats after the ring in dynamic LDS.  The epilogue's weighted sums
+// read it from there, and the perturbations never go to HBM (eq. (37)'s
+// weights are only known once every cost is, so the tile must be kept until
+// then; on chip it costs neither the store and re-read nor the write-back of
+// the L2 lines that the release fence would otherwise flush).  Used for the
+// one-channel models when the ring and the tile fit beside the kernel's
+// static LDS (T <= 496).  The 12-state model's tile (400 rows at T = 100)
+// and its 16-step ring do not fit together; with 8-step ring slots they do,
+// but measured slower than the HBM round trip (K=8192, T=100: 52.1 against
+// 51.1 us), so it keeps the tile in HBM.
+constexpr size_t kLdsBytes = 160 * 1024;     // LDS of a gfx950 compute unit
+constexpr size_t kWsStaticLds = 20 * 1024;   // bound on the kernel's static LDS
+template <int DYN>
+constexpr size_t ws_eps_lds_bytes(int R) {
+  return ws_ring_bytes<DYN>() + sizeof(float) * (size_t)R * kWsSamples;
+}
+template <int DYN>
+constexpr bool ws_eps_fits(int R) {
+  return Model<DYN>::M == 1 && ws_eps_lds_bytes<DYN>(R) + kWsStaticLds <= kLdsBytes;
+}
+
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FULL, bool EPS_LDS>
 __device__ __forceinline__ void ws_produce(const DevParams& p, const Consts& cs, const Buffers& b,
-                                           const float* U, float* slot, int t,
+                                           const float* U, float* slot, float* epsl, int t,
                                            int k, bool active, uint32_t it) {
   using Md = Model<DYN>;
   using Rg = WsRing<DYN>;
@@ -96,8 +119,13 @@ __device__ __forceinline__ void ws_produce(const DevParams& p, const Consts& cs,
 #pragma unroll
   for (int i = 0; i < Rg::NG; ++i) slot[(M + i) * 64 + lane] = nz.gust[i];
   slot[(Rg::NF - 1) * 64 + lane] = state_free_cost<M, FORM, FULL>(p, cs, u, nz.eps);
+  if constexpr (EPS_LDS) {
 #pragma unroll
-  for (int j = 0; j < M; ++j) b.eps[(size_t)(t * M + j) * p.Ks + k] = nz.eps[j];
+    for (int j = 0; j < M; ++j) epsl[(t * M + j) * kWsSamples + lane] = nz.eps[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < M; ++j) b.eps[(size_t)(t * M + j) * p.Ks + k] = nz.eps[j];
+  }
   if constexpr (DEBUG) {
     if (active) {
       const size_t kt = (size_t)k * p.T + t;
@@ -163,7 +191,8 @@ __device__ __forceinline__ void ws_consume(const DevParams& p, const Consts& cs,
 }
 
 // One workgroup (tile wg of nwg) of the wave-specialised rollout, W waves.
-template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, int W, bool FULL = false>
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, int W, bool FULL = false,
+          bool EPS_LDS = false>
 __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffers& b,
                                                 const float* __restrict__ x0,
                                                 const float* U, int R,
@@ -171,18 +200,22 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
   using Md = Model<DYN>;
   using Rg = WsRing<DYN>;
   constexpr int N = Md::N;
+  static_assert(!EPS_LDS || FUSED, "the on-chip tile serves the fused epilogue");
   constexpr int NP = W - 1;  // producer waves
+  constexpr int CH = kWsChunk;
   constexpr int SLOT = Rg::NF * 64;  // floats per (step) slot
-  // the ring lives in dynamic LDS (ws_ring_bytes<DYN>() at launch), so that
-  // kernels containing several model variants share one allocation
+  // the ring lives in dynamic LDS (ws_ring_bytes<DYN>() at launch, plus the
+  // perturbation tile with EPS_LDS), so that kernels containing several
+  // model variants share one allocation
   extern __shared__ float ws_dyn_lds[];
-  float(*ring)[kWsChunk][SLOT] = reinterpret_cast<float(*)[kWsChunk][SLOT]>(ws_dyn_lds);
+  float(*ring)[CH][SLOT] = reinterpret_cast<float(*)[CH][SLOT]>(ws_dyn_lds);
+  float* epsl = ws_dyn_lds + 2 * CH * SLOT;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int k = wg * kWsSamples + lane;
   const bool active = k < p.K;
   const uint32_t it = (uint32_t)b.stats->iteration;
   const int T = p.T;
-  const int nch = (T + kWsChunk - 1) / kWsChunk;
+  const int nch = (T + CH - 1) / CH;
   __shared__ Consts cs;
   stage_consts(cs, p);
 
@@ -210,15 +243,17 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
       float(*buf)[SLOT] = ring[c & 1];
       if constexpr (W == 8) {
         for (int s = s0; s < s1; ++s) {
-          const int t = c * kWsChunk + s;
+          const int t = c * CH + s;
           if (t < T)
-            ws_produce<DYN, JUMPS, DEBUG, FORM, FULL>(p, cs, b, U, buf[s], t, k, active, it);
+            ws_produce<DYN, JUMPS, DEBUG, FORM, FULL, EPS_LDS>(p, cs, b, U, buf[s], epsl, t, k,
+                                                                active, it);
         }
       } else {
-        for (int s = wave - 1; s < kWsChunk; s += NP) {
-          const int t = c * kWsChunk + s;
+        for (int s = wave - 1; s < CH; s += NP) {
+          const int t = c * CH + s;
           if (t < T)
-            ws_produce<DYN, JUMPS, DEBUG, FORM, FULL>(p, cs, b, U, buf[s], t, k, active, it);
+            ws_produce<DYN, JUMPS, DEBUG, FORM, FULL, EPS_LDS>(p, cs, b, U, buf[s], epsl, t, k,
+                                                                active, it);
         }
       }
       __syncthreads();
@@ -229,11 +264,11 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
     __syncthreads();
     for (int cc = 0; cc < nch; ++cc) {
       float(*buf)[SLOT] = ring[cc & 1];
-      if ((cc + 1) * kWsChunk <= T) {
+      if ((cc + 1) * CH <= T) {
 #pragma unroll kUnroll
-        for (int s = 0; s < kWsChunk; ++s) ws_consume<DYN>(p, cs, st, buf[s]);
+        for (int s = 0; s < CH; ++s) ws_consume<DYN>(p, cs, st, buf[s]);
       } else {
-        for (int s = 0; s < T - cc * kWsChunk; ++s) ws_consume<DYN>(p, cs, st, buf[s]);
+        for (int s = 0; s < T - cc * CH; ++s) ws_consume<DYN>(p, cs, st, buf[s]);
       }
       __syncthreads();
     }
@@ -252,17 +287,22 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
     Sd = (double)st.S - (double)st.comp;
     if (active) b.S[k] = Sd;
   }
-  rollout_epilogue<kWsSamples, FUSED, 64 * W>(p, b, Sd, wave == 0 && active, R, sh, wg, nwg);
+  // the epilogue's weighted sums read the tile on chip, or the workgroup's
+  // columns of the HBM perturbations
+  const float* tile = EPS_LDS ? epsl : b.eps + (size_t)wg * kWsSamples;
+  const int tstride = EPS_LDS ? kWsSamples : p.Ks;
+  rollout_epilogue<kWsSamples, FUSED, 64 * W>(p, b, Sd, wave == 0 && active, R, sh, wg, nwg,
+                                              tile, tstride);
 }
 
-template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL>
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL, bool EPS_LDS>
 __global__ __launch_bounds__(64 * WsWaves<DYN>::W) void rollout_ws_kernel(const DevParams p,
                                                                          const Buffers b,
                                                                          const float* __restrict__ x0,
                                                                          const float* U,
                                                                          int R, const ShiftArgs sh) {
-  rollout_ws_tile<DYN, JUMPS, DEBUG, FORM, FUSED, WsWaves<DYN>::W, FULL>(p, b, x0, U, R, sh, blockIdx.x,
-                                                                   gridDim.x);
+  rollout_ws_tile<DYN, JUMPS, DEBUG, FORM, FUSED, WsWaves<DYN>::W, FULL, EPS_LDS>(
+      p, b, x0, U, R, sh, blockIdx.x, gridDim.x);
 }
 
 }  // namespace mppi

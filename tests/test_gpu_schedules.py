@@ -17,6 +17,9 @@ WS = native.C["MPPI_SCHED_WAVE_SPECIALISED"]
 
 
 def _run(cfg, U0, x0, iters, staged=False):
+    """(S, U, eps, W, stats) after `iters` iterations; eps is None where the
+    iterations kept the perturbations on chip (fused wave-specialised form)
+    and stored none."""
     ctl = Controller(cfg, U0)
     if staged:
         for _ in range(iters):
@@ -24,8 +27,14 @@ def _run(cfg, U0, x0, iters, staged=False):
             ctl.update()
     else:
         ctl.step(x0, iters)
-    return (ctl.S.cpu().numpy(), ctl.U.cpu().numpy(), ctl.eps.cpu().numpy(),
-            ctl.W.cpu().numpy(), ctl.stats())
+    try:
+        eps = ctl.eps.cpu().numpy()
+    except native.MppiError as e:
+        # only a fused wave-specialised iteration keeps them on chip
+        assert e.code == native.C["MPPI_EUNSUPPORTED"] and not staged
+        assert cfg.get("schedule", 0) != LANE
+        eps = None
+    return (ctl.S.cpu().numpy(), ctl.U.cpu().numpy(), eps, ctl.W.cpu().numpy(), ctl.stats())
 
 
 @pytest.mark.parametrize("preset,K,T", [
@@ -46,7 +55,12 @@ def test_schedules_and_update_paths_agree(preset, K, T):
     ref = _run(dict(cfg, schedule=LANE), U0, x0, 1)
     for sched, staged in ((WS, False), (LANE, True), (WS, True)):
         S, U, eps, W, st = _run(dict(cfg, schedule=sched), U0, x0, 1, staged)
-        assert np.array_equal(S, ref[0]) and np.array_equal(eps, ref[2]), (sched, staged)
+        assert np.array_equal(S, ref[0]), (sched, staged)
+        # fused wave-specialised iterations of the one-channel models keep
+        # eps on chip (T <= 496); the quadrotor stores it
+        assert (eps is None) == (sched == WS and not staged and cfg["dynamics"] != 2
+                                 and T <= 496), (sched, staged)
+        assert eps is None or np.array_equal(eps, ref[2]), (sched, staged)
         np.testing.assert_array_max_ulp(U, ref[1], maxulp=1)
         assert np.allclose(W, ref[3], rtol=1e-12, atol=1e-300)
         assert st["rho"] == ref[4]["rho"] and st["n_finite"] == ref[4]["n_finite"]
@@ -72,6 +86,7 @@ def test_large_K_uses_lane_schedule_and_staged_update():
     x0 = workloads.x0_for(cfg)
     a = _run(cfg, U0, x0, 1)
     b = _run(dict(cfg, schedule=WS), U0, x0, 1)
+    assert a[2] is not None and b[2] is not None  # unfused: both store them
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
     np.testing.assert_array_max_ulp(a[1], b[1], maxulp=1)
     W = a[3]
