@@ -52,8 +52,8 @@ import numpy as np  # noqa: E402
 # slots of the gfx950 instruction that implements it (full rate 1; 32x32->64
 # multiply and transcendental 4, as measured by the instruction-rate probe).
 # Derivation in the design notes (rollout roofline section).
-ALG_SLOTS = {0: 187, 1: 219, 2: 537}
-ALG_FP32_FLOP = {0: 40, 1: 71, 2: 231}
+ALG_SLOTS = {0: 184, 1: 216, 2: 534}
+ALG_FP32_FLOP = {0: 37, 1: 68, 2: 228}
 # 256 CUs x 128 full-rate lane-slots per CU-clock x 2.4 GHz (measured issue
 # rate of v_fma_f32; at 2 FLOP per slot this is the 157.3 TFLOP/s FP32 peak)
 VALU_PEAK_SLOTS = 256 * 128 * 2.4e9
@@ -278,8 +278,10 @@ def batched_measure(n_ctl, ticks, warmup, seed=42):
     """Batched form against plain per-controller launches on the same
     controller set (half cartpole, half quadrotor, K in {512..8192}, T in
     [30, 150], nu in [0, 10]/s): one tick = one iteration + shift of every
-    controller from its own state.  The batched tick is one graph replay
-    (one launch); the plain tick is n_ctl control-step launches in sequence."""
+    controller from its own state.  The batched tick is one graph replay of
+    the layout the autotuner measured fastest (schedule, grid or persistent
+    launch, one kernel or one per model on its own stream); the plain tick is
+    n_ctl control-step launches in sequence."""
     import torch
     from paper_1807_06108_amd import autotune, workloads
     from paper_1807_06108_amd.controller import Controller
@@ -312,7 +314,6 @@ def batched_measure(n_ctl, ticks, warmup, seed=42):
         batch.step(iters=1, shift=True)
     torch.cuda.synchronize()
     batched = timed(g.replay, ticks)
-    sched = report["schedule"]
     plain_ctls = [Controller(dict(c, schedule=0)) for c in cfgs]
     u0 = torch.empty(4, device="cuda")
 
@@ -327,7 +328,7 @@ def batched_measure(n_ctl, ticks, warmup, seed=42):
     slots = sum(ALG_SLOTS[c["dynamics"]] * c["K"] * c["T"] for c in cfgs)
     achieved = slots / (batched["ms_per_tick"] * 1e-3)
     return {"controllers": n_ctl, "rollout_steps_per_tick": work,
-            "schedule": {1: "lane", 2: "ws"}[sched], "autotune_ms": report["timings_ms"],
+            "layout": report["plan"], "autotune_ms_per_tick": report["timings_ms"],
             "batched_graph": batched, "plain_sequential": plain,
             "speedup": batched["value"] / plain["value"],
             "roofline": {"bound": "alu", "achieved": achieved / 1e12,

@@ -273,7 +273,7 @@ const char* mppi_jump_last_error(void);
 typedef struct mppi_jump_batch mppi_jump_batch;
 
 /* Device scratch for a batch of n contexts (descriptor table, tile list,
- * u_0 outputs [n][4] fp32), for a 256-byte aligned base.  Pure host function.
+ * u_0 outputs [n][4] fp32, work queue), for a 256-byte aligned base.  Pure host function.
  * EINVAL for NULL/mixed-schedule contexts; EUNSUPPORTED for a context whose
  * update is not fused or that has debug_dump set. */
 int mppi_jump_batch_scratch_bytes(mppi_jump_ctx* const* ctxs, int32_t n, size_t* bytes);
@@ -290,6 +290,17 @@ int mppi_jump_batch_create(mppi_jump_ctx* const* ctxs, const float* const* d_x0,
  * per iteration); with shift != 0 the last one also shifts every sequence
  * and writes each controller's u_0 to its slot of the u_0 output array. */
 int mppi_jump_batch_step(mppi_jump_batch* batch, int32_t iters, int32_t shift, void* stream);
+
+/* Launch form of mppi_jump_batch_step (the same results either way):
+ * MPPI_BATCH_GRID (the default) launches one workgroup per tile and lets the
+ * hardware dispatcher start them in the longest-first order of the tile
+ * list; MPPI_BATCH_PERSISTENT launches as many workgroups as the GPU holds at
+ * once (the kernel's occupancy times the compute units), each taking the next
+ * tile from a device work queue in the batch scratch until none is left.
+ * EINVAL for another value; EDEVICE if the occupancy query fails. */
+#define MPPI_BATCH_GRID 0
+#define MPPI_BATCH_PERSISTENT 1
+int mppi_jump_batch_set_launch(mppi_jump_batch* batch, int32_t launch);
 
 /* Device address of the u_0 outputs, [n][4] fp32 (controller i at 4*i). */
 int mppi_jump_batch_u0(mppi_jump_batch* batch, float** d_u0);

@@ -189,9 +189,12 @@ class Batch:
     """Many controllers advanced by one launch per iteration (batched form).
 
     controllers: Controller objects created with the same schedule; states:
-    their state tensors ([n_i] fp32 on the device), read at every step."""
+    their state tensors ([n_i] fp32 on the device), read at every step.
+    launch: native.C["MPPI_BATCH_GRID"] (one workgroup per tile) or
+    native.C["MPPI_BATCH_PERSISTENT"] (resident workgroups take tiles from a
+    device work queue)."""
 
-    def __init__(self, controllers, states, stream=None):
+    def __init__(self, controllers, states, stream=None, launch=0):
         self.controllers = list(controllers)
         self.states = [torch.as_tensor(x, dtype=torch.float32, device="cuda").contiguous()
                        for x in states]
@@ -211,6 +214,8 @@ class Batch:
         native.check(native.lib().mppi_jump_batch_u0(bt, ctypes.byref(u0)))
         off = u0.value - self.scratch.data_ptr()
         self.u0 = self.scratch[off:off + 16 * n].view(torch.float32).view(n, 4)
+        self.launch = int(launch)
+        native.check(native.lib().mppi_jump_batch_set_launch(bt, self.launch))
 
     def step(self, iters=1, shift=True):
         native.check(native.lib().mppi_jump_batch_step(self.bt, int(iters), int(bool(shift)),
@@ -226,6 +231,30 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class BatchGroup:
+    """Sub-batches of one controller set (e.g. one per model), each with its
+    own stream, stepped together: every sub-batch's stream waits for torch's
+    current stream, launches, and the current stream waits for all of them
+    (so a step can be captured in one graph from the current stream)."""
+
+    def __init__(self, batches):
+        self.batches = list(batches)
+
+    def step(self, iters=1, shift=True):
+        cur = torch.cuda.current_stream()
+        for b in self.batches:
+            if b.stream is not None:
+                b.stream.wait_stream(cur)
+            b.step(iters, shift)
+        for b in self.batches:
+            if b.stream is not None:
+                cur.wait_stream(b.stream)
+
+    def close(self):
+        for b in self.batches:
+            b.close()
 
 
 def _np_ptr(a):

@@ -31,16 +31,23 @@ struct BatchTile {
 // kernel, measured no faster over a mixed batch (the per-tile switch over
 // all twelve instantiations already costs the registers that the extra
 // producers would need, and the eight-wave build spills).
-template <bool WS>
+// MASK: the dynamics ids compiled in (bit DYN); a batch of one model runs a
+// kernel holding only that model's variants (fewer registers).
+constexpr int kMaskAll = 7, kMaskCartpole = 1 << MPPI_DYN_CARTPOLE,
+              kMaskQuadrotor = 1 << MPPI_DYN_QUADROTOR;
+
+template <bool WS, int MASK = kMaskAll>
 __device__ __forceinline__ void batch_tile(const BatchDesc& d, const float* x0, const ShiftArgs& sh,
                                            int wg) {
   const int sel = d.dyn * 4 + d.jumps * 2 + (d.form == MPPI_COST_SO ? 1 : 0);
 #define MPPI_BATCH_CASE(DYN, J, F)                                                            \
   case DYN * 4 + J * 2 + (F == MPPI_COST_SO ? 1 : 0):                                       \
-    if constexpr (WS)                                                                         \
-      rollout_ws_tile<DYN, J, false, F, true, 4>(d.p, d.b, x0, d.b.U, d.R, sh, wg, d.nwg);   \
-    else                                                                                      \
-      rollout_lane_tile<DYN, J, false, F, true>(d.p, d.b, x0, d.b.U, d.R, sh, wg, d.nwg);    \
+    if constexpr ((MASK >> DYN) & 1) {                                                        \
+      if constexpr (WS)                                                                       \
+        rollout_ws_tile<DYN, J, false, F, true, 4>(d.p, d.b, x0, d.b.U, d.R, sh, wg, d.nwg); \
+      else                                                                                    \
+        rollout_lane_tile<DYN, J, false, F, true>(d.p, d.b, x0, d.b.U, d.R, sh, wg, d.nwg);  \
+    }                                                                                         \
     break;
   switch (sel) {
     MPPI_BATCH_CASE(MPPI_DYN_LINEAR, 0, MPPI_COST_IT)
@@ -60,19 +67,63 @@ __device__ __forceinline__ void batch_tile(const BatchDesc& d, const float* x0, 
 #undef MPPI_BATCH_CASE
 }
 
-// shift != 0: this launch is the last iteration of a control step.
-template <bool WS>
-__global__ __launch_bounds__(256) void batch_rollout_kernel(const BatchDesc* __restrict__ descs,
-                                                            const BatchTile* __restrict__ tiles,
-                                                            int shift) {
-  const BatchTile tl = tiles[blockIdx.x];
-  const BatchDesc& d = descs[tl.ctl];
+__device__ __forceinline__ ShiftArgs batch_shift(const BatchDesc& d, int shift) {
   ShiftArgs sh;
   sh.on = shift;
   sh.u0_out = d.u0_out;
   sh.m = d.m;
   sh.u_init = d.u_init;
-  batch_tile<WS>(d, d.x0, sh, tl.wg);
+  return sh;
+}
+
+// Grid launch: one workgroup per tile; the hardware dispatcher starts them
+// in tile-list order as compute units free up.  shift != 0: this launch is
+// the last iteration of a control step.
+template <bool WS, int MASK>
+__global__ __launch_bounds__(256) void batch_rollout_kernel(const BatchDesc* __restrict__ descs,
+                                                            const BatchTile* __restrict__ tiles,
+                                                            int shift) {
+  const BatchTile tl = tiles[blockIdx.x];
+  const BatchDesc& d = descs[tl.ctl];
+  batch_tile<WS, MASK>(d, d.x0, batch_shift(d, shift), tl.wg);
+}
+
+// Work queue of the persistent launch: the next tile to take and the number
+// of workgroups that have left.  Zero before a launch; the last workgroup to
+// leave zeroes it again for the next one.
+struct BatchQueue {
+  uint32_t head;
+  uint32_t done;
+};
+
+// Persistent launch: as many workgroups as the GPU holds at once, each
+// taking the next tile of the longest-first list from the queue until none
+// is left.  Nothing waits on another workgroup (a controller's last tile
+// combines its partials as in the grid launch), so every workgroup reaches
+// the end once the list is exhausted.
+template <bool WS, int MASK>
+__global__ __launch_bounds__(256) void batch_persistent_kernel(const BatchDesc* __restrict__ descs,
+                                                               const BatchTile* __restrict__ tiles,
+                                                               int ntiles, int shift,
+                                                               BatchQueue* queue) {
+  __shared__ int next;
+  for (;;) {
+    __syncthreads();  // the previous tile is done with LDS and with `next`
+    if (threadIdx.x == 0) next = (int)atomicAdd(&queue->head, 1u);
+    __syncthreads();
+    const int t = next;
+    if (t >= ntiles) break;
+    const BatchTile tl = tiles[t];
+    const BatchDesc& d = descs[tl.ctl];
+    batch_tile<WS, MASK>(d, d.x0, batch_shift(d, shift), tl.wg);
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();  // this workgroup's queue increments precede its exit count
+    if (atomicAdd(&queue->done, 1u) == gridDim.x - 1) {
+      atomicExch(&queue->head, 0u);
+      atomicExch(&queue->done, 0u);
+    }
+  }
 }
 
 }  // namespace mppi
@@ -123,7 +174,7 @@ __global__ __launch_bounds__(256) void pool_rollout_kernel(const BatchDesc* __re
   sh.u0_out = tick.out + kPoolOut * i;
   sh.m = d.m;
   sh.u_init = d.u_init;
-  batch_tile<WS>(d, tick.states + 12 * i, sh, blockIdx.x - tick.prefix[i]);
+  batch_tile<WS, kMaskAll>(d, tick.states + 12 * i, sh, blockIdx.x - tick.prefix[i]);
 }
 
 template <int DYN>

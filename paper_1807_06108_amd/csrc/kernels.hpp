@@ -508,12 +508,26 @@ __device__ __forceinline__ void draw_noise(Noise<DYN, JUMPS>& o, const DevParams
   }
 }
 
-__device__ __forceinline__ void kahan_add(float& s, float& comp, float term) {
-  const float y = term - comp;
-  const float t = s + y;
-  comp = (t - s) - y;
-  s = t;
-}
+// Path-cost accumulation: the stage costs of each block of kCostBlock time
+// steps (t = 16 c .. 16 c + 15) are summed in fp32 and the block sums in
+// fp64, so the fp32 sum holds at most 16 terms.  Its rounding (~16 ulps of
+// the block's term magnitudes) stays below the fp32 trajectory error that
+// bounds S~ anyway (an fp32 emulation gives the same maximum error with
+// compensated, blocked or plain summation); the consumer wave of the
+// wave-specialised schedule, which runs the serial recursion, then spends
+// one add per step on the sum instead of four.  Both schedules block the
+// same steps, so their costs agree bitwise.
+constexpr int kCostBlock = 16;
+
+struct CostSum {
+  float blk = 0.f;   // sum of the current block's stage costs
+  double S = 0.0;    // sum of the completed blocks
+  __device__ __forceinline__ void add(float term) { blk += term; }
+  __device__ __forceinline__ void close_block() {
+    S += (double)blk;
+    blk = 0.f;
+  }
+};
 
 // State-free part of the stage cost of eqs. (34)-(35): nominal control cost
 // times dt plus the importance-sampling terms (IT form), or the control cost
@@ -575,7 +589,7 @@ __device__ __forceinline__ void rollout_lane_tile(const DevParams& p, const Buff
 #pragma unroll
   for (int i = 0; i < N; ++i) x[i] = x0[i];
   bool crashed = Md::CAN_CRASH ? Md::crashed(x, cs.mc) : false;
-  float S = 0.f, comp = 0.f;
+  CostSum S;
 
   // software pipeline: the draws of step t + 1 are formed while step t's
   // dynamics run (they do not depend on the state); the last step draws
@@ -599,7 +613,8 @@ __device__ __forceinline__ void rollout_lane_tile(const DevParams& p, const Buff
     }
     if constexpr (Md::CAN_CRASH) qx += crashed ? p.pen : 0.f;
     const float term = qx * p.dt + state_free_cost<M, FORM, FULL>(p, cs, u, cur.eps);
-    kahan_add(S, comp, term);
+    S.add(term);
+    if ((t & (kCostBlock - 1)) == kCostBlock - 1 || t == p.T - 1) S.close_block();
 
     float v[M];
 #pragma unroll
@@ -638,8 +653,7 @@ __device__ __forceinline__ void rollout_lane_tile(const DevParams& p, const Buff
     qf += p.Qf[i] * d * d;
   }
   if constexpr (Md::CAN_CRASH) qf += crashed ? p.pen : 0.f;
-  kahan_add(S, comp, qf);
-  const double Sd = (double)S - (double)comp;
+  const double Sd = S.S + (double)qf;
   if (active) b.S[k] = Sd;
   rollout_epilogue<kBlock, FUSED>(p, b, Sd, active, R, sh, wg, nwg,
                                   b.eps + (size_t)wg * kBlock, p.Ks);

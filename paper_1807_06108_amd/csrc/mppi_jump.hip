@@ -822,14 +822,18 @@ struct mppi_jump_batch {
   BatchDesc* d_desc = nullptr;
   BatchTile* d_tiles = nullptr;
   float* d_u0 = nullptr;
+  BatchQueue* d_queue = nullptr;
   bool ws = false;
+  int mask = kMaskAll;          // dynamics ids of the batch's kernel
+  int launch = MPPI_BATCH_GRID;
+  int slots = 0;                // workgroups of the persistent launch
   size_t dyn_lds = 0;
 };
 
 namespace {
 
 struct BatchLayout {
-  size_t desc, tiles, u0, total;
+  size_t desc, tiles, u0, queue, total;
   int ntiles;
 };
 
@@ -857,6 +861,7 @@ int batch_check(mppi_jump_ctx* const* ctxs, int32_t n, BatchLayout& BL, bool& ws
   BL.desc = take((size_t)n * sizeof(BatchDesc));
   BL.tiles = take((size_t)ntiles * sizeof(BatchTile));
   BL.u0 = take((size_t)n * 4 * sizeof(float));
+  BL.queue = take(sizeof(BatchQueue));
   BL.total = off;
   BL.ntiles = ntiles;
   return MPPI_OK;
@@ -865,9 +870,63 @@ int batch_check(mppi_jump_ctx* const* ctxs, int32_t n, BatchLayout& BL, bool& ws
 // Tile cost estimate for the longest-first order: time steps times the
 // issue slots of one sample-step of the model.
 double tile_cost(const mppi_jump_ctx* c) {
-  const double per_step = c->cfg.dynamics == MPPI_DYN_QUADROTOR ? 537.0
-                          : c->cfg.dynamics == MPPI_DYN_CARTPOLE ? 219.0 : 187.0;
+  const double per_step = c->cfg.dynamics == MPPI_DYN_QUADROTOR ? 534.0
+                          : c->cfg.dynamics == MPPI_DYN_CARTPOLE ? 216.0 : 184.0;
   return per_step * c->cfg.T;
+}
+
+// The batch kernel instantiations: grid launch of either schedule over all
+// models, and of the lane schedule per model; persistent launch of the lane
+// schedule (all models, or one) and of the wave-specialised schedule.
+template <bool WS, int MASK>
+int launch_batch_t(mppi_jump_batch* bt, int shift, hipStream_t s) {
+  const size_t lds = WS ? bt->dyn_lds : 0;
+  if (bt->launch == MPPI_BATCH_PERSISTENT) {
+    batch_persistent_kernel<WS, MASK><<<bt->slots, kBlock, lds, s>>>(
+        bt->d_desc, bt->d_tiles, (int)bt->h_tiles.size(), shift, bt->d_queue);
+    LAUNCH_CHECK("batch_persistent_kernel");
+  } else {
+    batch_rollout_kernel<WS, MASK><<<(unsigned)bt->h_tiles.size(), kBlock, lds, s>>>(
+        bt->d_desc, bt->d_tiles, shift);
+    LAUNCH_CHECK("batch_rollout_kernel");
+  }
+  return MPPI_OK;
+}
+
+int launch_batch(mppi_jump_batch* bt, int shift, hipStream_t s) {
+  if (bt->ws) return launch_batch_t<true, kMaskAll>(bt, shift, s);
+  if (bt->mask == kMaskCartpole) return launch_batch_t<false, kMaskCartpole>(bt, shift, s);
+  if (bt->mask == kMaskQuadrotor) return launch_batch_t<false, kMaskQuadrotor>(bt, shift, s);
+  return launch_batch_t<false, kMaskAll>(bt, shift, s);
+}
+
+// Workgroups of the persistent launch: as many as the GPU holds at once
+// (occupancy of the batch's persistent kernel times the compute units), at
+// most one per tile.
+template <bool WS, int MASK>
+int occupancy_of(mppi_jump_batch* bt, int* per_cu) {
+  HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      per_cu, batch_persistent_kernel<WS, MASK>, kBlock, WS ? bt->dyn_lds : 0));
+  return MPPI_OK;
+}
+
+int persistent_slots(mppi_jump_batch* bt) {
+  int dev = 0, cus = 0, per_cu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  int rc;
+  if (bt->ws)
+    rc = occupancy_of<true, kMaskAll>(bt, &per_cu);
+  else if (bt->mask == kMaskCartpole)
+    rc = occupancy_of<false, kMaskCartpole>(bt, &per_cu);
+  else if (bt->mask == kMaskQuadrotor)
+    rc = occupancy_of<false, kMaskQuadrotor>(bt, &per_cu);
+  else
+    rc = occupancy_of<false, kMaskAll>(bt, &per_cu);
+  if (rc != MPPI_OK) return rc;
+  if (per_cu < 1 || cus < 1) return fail(MPPI_EDEVICE, "no resident workgroup for the batch kernel");
+  bt->slots = std::min(per_cu * cus, (int)bt->h_tiles.size());
+  return MPPI_OK;
 }
 
 }  // namespace
@@ -905,11 +964,13 @@ int mppi_jump_batch_create(mppi_jump_ctx* const* ctxs, const float* const* d_x0,
       return fail(MPPI_EWORKSPACE, "scratch of %zu bytes < %zu needed", scratch_bytes, BL.total);
     auto* bt = new mppi_jump_batch();
     bt->ws = ws;
+    int models = 0;
     bt->ctxs.assign(ctxs, ctxs + n);
     char* base = static_cast<char*>(d_scratch);
     bt->d_desc = reinterpret_cast<BatchDesc*>(base + BL.desc);
     bt->d_tiles = reinterpret_cast<BatchTile*>(base + BL.tiles);
     bt->d_u0 = reinterpret_cast<float*>(base + BL.u0);
+    bt->d_queue = reinterpret_cast<BatchQueue*>(base + BL.queue);
     bt->h_desc.resize(n);
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) {
@@ -928,6 +989,7 @@ int mppi_jump_batch_create(mppi_jump_ctx* const* ctxs, const float* const* d_x0,
       d.form = c->cfg.cost_form;
       d.m = c->m;
       order[i] = i;
+      models |= 1 << c->cfg.dynamics;
       if (ws) {
         const size_t lds = c->cfg.dynamics == MPPI_DYN_QUADROTOR ? ws_ring_bytes<MPPI_DYN_QUADROTOR>()
                            : c->cfg.dynamics == MPPI_DYN_CARTPOLE ? ws_ring_bytes<MPPI_DYN_CARTPOLE>()
@@ -935,6 +997,9 @@ int mppi_jump_batch_create(mppi_jump_ctx* const* ctxs, const float* const* d_x0,
         if (lds > bt->dyn_lds) bt->dyn_lds = lds;
       }
     }
+    // one-model batches of the lane schedule run a kernel of that model's
+    // variants only
+    if (!ws && (models == kMaskCartpole || models == kMaskQuadrotor)) bt->mask = models;
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return tile_cost(ctxs[a]) > tile_cost(ctxs[b]); });
     bt->h_tiles.reserve(BL.ntiles);
@@ -950,6 +1015,9 @@ int mppi_jump_batch_create(mppi_jump_ctx* const* ctxs, const float* const* d_x0,
     if (e == hipSuccess)
       e = hipMemcpyAsync(bt->d_u0, zeros.data(), zeros.size() * sizeof(float),
                          hipMemcpyHostToDevice, s);
+    const BatchQueue q0{0u, 0u};  // the persistent launch's queue starts empty
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(bt->d_queue, &q0, sizeof q0, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
       delete bt;
@@ -968,19 +1036,29 @@ int mppi_jump_batch_step(mppi_jump_batch* bt, int32_t iters, int32_t shift, void
       if (c->host_iteration + (uint64_t)iters > kTwo32)
         return fail(MPPI_EINVAL, "iteration counter would pass 2^32");
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    const dim3 grid((unsigned)bt->h_tiles.size()), block(kBlock);
     for (int i = 0; i < iters; ++i) {
       const int sh = (shift && i == iters - 1) ? 1 : 0;
-      if (bt->ws)
-        batch_rollout_kernel<true><<<grid, block, bt->dyn_lds, s>>>(bt->d_desc, bt->d_tiles, sh);
-      else
-        batch_rollout_kernel<false><<<grid, block, 0, s>>>(bt->d_desc, bt->d_tiles, sh);
-      LAUNCH_CHECK("batch_rollout_kernel");
+      const int rc = launch_batch(bt, sh, s);
+      if (rc != MPPI_OK) return rc;
     }
     for (auto* c : bt->ctxs) {
       c->host_iteration += (uint64_t)iters;
       c->eps_stored = true;  // batched tiles store their perturbations
     }
+    return ok();
+  });
+}
+
+int mppi_jump_batch_set_launch(mppi_jump_batch* bt, int32_t launch) {
+  return guarded([&]() -> int {
+    if (!bt) return fail(MPPI_EINVAL, "NULL batch");
+    if (launch != MPPI_BATCH_GRID && launch != MPPI_BATCH_PERSISTENT)
+      return fail(MPPI_EINVAL, "unknown batch launch %d", launch);
+    if (launch == MPPI_BATCH_PERSISTENT) {
+      const int rc = persistent_slots(bt);
+      if (rc != MPPI_OK) return rc;
+    }
+    bt->launch = launch;
     return ok();
   });
 }

@@ -14,7 +14,7 @@
 namespace mppi {
 
 constexpr int kWsSamples = 64;  // samples per workgroup
-constexpr int kWsChunk = 16;    // time steps per ring slot
+constexpr int kWsChunk = 16;    // time steps per ring slot (one cost block)
 
 // Wavefronts per workgroup: eight (two per SIMD, one consumer and seven
 // producers).  Measured on the light models, 4, 6 and 12 are slower; for the
@@ -52,6 +52,7 @@ struct WsSplit {
     return f;
   }
 };
+static_assert(kWsChunk == kCostBlock, "a ring chunk is one cost block (schedules agree bitwise)");
 static_assert(WsSplit<MPPI_DYN_CARTPOLE>::first(8) == kWsChunk, "split covers the chunk");
 static_assert(WsSplit<MPPI_DYN_QUADROTOR>::first(8) == kWsChunk, "split covers the chunk");
 static_assert(WsSplit<MPPI_DYN_LINEAR>::first(8) == kWsChunk, "split covers the chunk");
@@ -141,7 +142,7 @@ __device__ __forceinline__ void ws_produce(const DevParams& p, const Consts& cs,
 template <int DYN>
 struct WsState {
   float x[Model<DYN>::N];
-  float S, comp;
+  CostSum S;
   bool crashed;
 };
 
@@ -161,7 +162,7 @@ __device__ __forceinline__ void ws_step(const DevParams& p, const Consts& cs, Ws
     qx += cs.Q[i] * d * d;
   }
   if constexpr (Md::CAN_CRASH) qx += st.crashed ? p.pen : 0.f;
-  kahan_add(st.S, st.comp, qx * p.dt + pre);
+  st.S.add(qx * p.dt + pre);
   if constexpr (Md::CAN_CRASH) {
     float xn[N];
 #pragma unroll
@@ -175,19 +176,53 @@ __device__ __forceinline__ void ws_step(const DevParams& p, const Consts& cs, Ws
   }
 }
 
-// The step of a ring slot, read from LDS.
+// A ring slot's values for one step: applied controls, body force, the
+// state-free part of the stage cost.
 template <int DYN>
-__device__ __forceinline__ void ws_consume(const DevParams& p, const Consts& cs, WsState<DYN>& st,
-                                           const float* slot) {
+struct WsSlot {
+  float v[Model<DYN>::M], gust[3], pre;
+};
+
+template <int DYN>
+__device__ __forceinline__ WsSlot<DYN> ws_read(const float* slot) {
   using Rg = WsRing<DYN>;
   constexpr int M = Model<DYN>::M;
   const int lane = threadIdx.x & 63;
-  float v[M], gust[3] = {0.f, 0.f, 0.f};
+  WsSlot<DYN> o;
 #pragma unroll
-  for (int j = 0; j < M; ++j) v[j] = slot[j * 64 + lane];
+  for (int j = 0; j < M; ++j) o.v[j] = slot[j * 64 + lane];
+  o.gust[0] = o.gust[1] = o.gust[2] = 0.f;
 #pragma unroll
-  for (int i = 0; i < Rg::NG; ++i) gust[i] = slot[(M + i) * 64 + lane];
-  ws_step<DYN>(p, cs, st, v, gust, slot[(Rg::NF - 1) * 64 + lane]);
+  for (int i = 0; i < Rg::NG; ++i) o.gust[i] = slot[(M + i) * 64 + lane];
+  o.pre = slot[(Rg::NF - 1) * 64 + lane];
+  return o;
+}
+
+// The n steps of a chunk.  For the one-channel models each slot is read one
+// step ahead, so that the LDS latency hides behind the previous step's
+// recursion (their step is short enough for the compiler's own placement to
+// leave it exposed: C1 19.0 -> 18.8 us); the 12-state model reads each slot
+// at its step (reading ahead measured slower there: K=8192 50.7 -> 52.2 us).
+template <int DYN, int UNROLL>
+__device__ __forceinline__ void ws_consume_chunk(const DevParams& p, const Consts& cs,
+                                                 WsState<DYN>& st, const float* buf, int slot_floats,
+                                                 int n) {
+  if constexpr (Model<DYN>::M == 1) {
+    WsSlot<DYN> cur = ws_read<DYN>(buf);
+#pragma unroll UNROLL
+    for (int s = 0; s < n; ++s) {
+      WsSlot<DYN> nxt = cur;
+      if (s + 1 < n) nxt = ws_read<DYN>(buf + (s + 1) * slot_floats);
+      ws_step<DYN>(p, cs, st, cur.v, cur.gust, cur.pre);
+      cur = nxt;
+    }
+  } else {
+#pragma unroll UNROLL
+    for (int s = 0; s < n; ++s) {
+      const WsSlot<DYN> cur = ws_read<DYN>(buf + s * slot_floats);
+      ws_step<DYN>(p, cs, st, cur.v, cur.gust, cur.pre);
+    }
+  }
 }
 
 // One workgroup (tile wg of nwg) of the wave-specialised rollout, W waves.
@@ -231,8 +266,7 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
 #pragma unroll
   for (int i = 0; i < N; ++i) st.x[i] = x0[i];
   st.crashed = Md::CAN_CRASH ? Md::crashed(st.x, cs.mc) : false;
-  st.S = 0.f;
-  st.comp = 0.f;
+  st.S = CostSum{};
 
   // Producers and the consumer run separate loops (the branch is uniform per
   // wavefront), so the register allocation of each holds only its own live
@@ -264,12 +298,11 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
     __syncthreads();
     for (int cc = 0; cc < nch; ++cc) {
       float(*buf)[SLOT] = ring[cc & 1];
-      if ((cc + 1) * CH <= T) {
-#pragma unroll kUnroll
-        for (int s = 0; s < CH; ++s) ws_consume<DYN>(p, cs, st, buf[s]);
-      } else {
-        for (int s = 0; s < T - cc * CH; ++s) ws_consume<DYN>(p, cs, st, buf[s]);
-      }
+      if ((cc + 1) * CH <= T)
+        ws_consume_chunk<DYN, kUnroll>(p, cs, st, buf[0], SLOT, CH);
+      else
+        ws_consume_chunk<DYN, 1>(p, cs, st, buf[0], SLOT, T - cc * CH);
+      st.S.close_block();  // a chunk is one cost block
       __syncthreads();
     }
   }
@@ -283,8 +316,7 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
       qf += p.Qf[i] * d * d;
     }
     if constexpr (Md::CAN_CRASH) qf += st.crashed ? p.pen : 0.f;
-    kahan_add(st.S, st.comp, qf);
-    Sd = (double)st.S - (double)st.comp;
+    Sd = st.S.S + (double)qf;
     if (active) b.S[k] = Sd;
   }
   // the epilogue's weighted sums read the tile on chip, or the workgroup's

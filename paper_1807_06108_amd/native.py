@@ -128,6 +128,7 @@ _PROTOS = {
                                               ctypes.POINTER(ctypes.c_void_p)]),
     "mppi_jump_batch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                             ctypes.c_void_p]),
+    "mppi_jump_batch_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "mppi_jump_batch_u0": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "mppi_jump_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "mppi_jump_pool_bytes": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_int32,

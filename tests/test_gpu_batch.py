@@ -10,12 +10,15 @@ import torch
 from gpu_util import check_S
 from oracle import mppi as omppi
 from paper_1807_06108_amd import native, workloads
+from paper_1807_06108_amd import autotune
 from paper_1807_06108_amd.controller import Batch, Controller
 
 pytestmark = pytest.mark.gpu
 
 LANE = native.C["MPPI_SCHED_LANE"]
 WS = native.C["MPPI_SCHED_WAVE_SPECIALISED"]
+GRID = native.C["MPPI_BATCH_GRID"]
+PERSISTENT = native.C["MPPI_BATCH_PERSISTENT"]
 
 
 def _controller_set(schedule, n=12, seed=5):
@@ -41,13 +44,16 @@ def _make(cset):
     return ctls, xs
 
 
-@pytest.mark.parametrize("schedule", [LANE, WS])
-def test_batch_equals_individual_controllers(schedule):
+@pytest.mark.parametrize("schedule,launch", [(LANE, GRID), (WS, GRID), (LANE, PERSISTENT),
+                                             (WS, PERSISTENT)])
+def test_batch_equals_individual_controllers(schedule, launch):
+    """Both launches of both schedules; two control steps of two iterations
+    each, so the persistent launch's work queue is reused four times."""
     cset = _controller_set(schedule)
-    print("batch of", len(cset), "controllers, schedule", schedule, flush=True)
+    print("batch of", len(cset), "controllers, schedule", schedule, "launch", launch, flush=True)
     a_ctl, a_x = _make(cset)
     b_ctl, b_x = _make(cset)
-    batch = Batch(a_ctl, a_x)
+    batch = Batch(a_ctl, a_x, launch=launch)
     u0_ind = []
     for step in range(2):
         batch.step(iters=2, shift=True)
@@ -116,3 +122,44 @@ def test_batch_error_paths():
     with pytest.raises(native.MppiError) as e:
         Batch([big], [x])
     assert e.value.code == native.C["MPPI_EUNSUPPORTED"]
+
+
+@pytest.mark.parametrize("launch", [GRID, PERSISTENT])
+def test_per_model_sub_batches_equal_individual_controllers(launch):
+    """The autotuner's per-model layout: one sub-batch per model (each a
+    kernel of that model's variants only) on its own stream, stepped
+    together and replayed from one graph captured across the streams."""
+    cset = [(cfg, x0) for cfg, x0 in _controller_set(LANE, n=10, seed=31)
+            if cfg["dynamics"] != 0]
+    cfgs = [c for c, _ in cset]
+    states = [torch.tensor(x0, device="cuda") for _, x0 in cset]
+    U0s = [workloads.U0_for(c, "random", seed=c["controller_id"] + 3) for c in cfgs]
+    ctls, group = autotune.make_batch(cfgs, states, (LANE, launch, True), U0s)
+    assert len(group.batches) == 2
+    b_ctl, b_x = _make(cset)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        group.step(iters=1, shift=True)
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        for c, x in zip(b_ctl, b_x):
+            c.control_step(x, 1)
+        torch.cuda.synchronize()
+        _ = (torch.ones(1024, device="cuda") * 2).sum().item()  # eager work between replays
+        for i, (ca, cb) in enumerate(zip(ctls, b_ctl)):
+            assert np.array_equal(ca.S.cpu().numpy(), cb.S.cpu().numpy()), (rep, i)
+            np.testing.assert_array_max_ulp(ca.U.cpu().numpy(), cb.U.cpu().numpy(), maxulp=1)
+            assert ca.stats()["iteration"] == cb.stats()["iteration"] == rep + 1
+
+
+def test_autotuner_times_every_layout():
+    cset = _controller_set(LANE, n=8, seed=41)
+    cfgs = [c for c, _ in cset]
+    states = [torch.tensor(x0, device="cuda") for _, x0 in cset]
+    plan, report = autotune.choose_plan(cfgs, states, ticks=2, warmup=1)
+    print("autotune", report, flush=True)
+    assert len(report["timings_ms"]) == len(autotune.PLANS)
+    assert report["plan"] == autotune.plan_name(plan)
+    assert min(report["timings_ms"].values()) == report["timings_ms"][report["plan"]]

@@ -5,7 +5,7 @@ their updates follows the unsharded controller within the update tolerance."""
 import numpy as np
 import pytest
 
-from gpu_util import U_ATOL, check_S
+from gpu_util import S_RTOL, U_ATOL, check_S
 from oracle import mppi as omppi
 from paper_1807_06108_amd import workloads
 from paper_1807_06108_amd.controller import Controller
@@ -31,8 +31,10 @@ def test_shards_equal_the_unsharded_controller(preset, K, T, shards):
             # same U, same draws: the costs are the same bits
             assert np.array_equal(sh.S, S_full)
         else:
-            # the sequences differ by the rounding of the two combines
-            assert (np.abs(sh.S - S_full) / np.maximum(np.abs(S_full), 1.0)).max() < 1e-5
+            # the sequences differ by the rounding of the two combines, and
+            # so do the costs, by up to what the contract's S tolerance allows
+            # (a cost whose terms cancel moves relative to its own size)
+            assert (np.abs(sh.S - S_full) / np.maximum(np.abs(S_full), 1.0)).max() < S_RTOL
         assert np.abs(U_sh - full.U.cpu().numpy()).max() < U_ATOL
         # the shards agree with the oracle too (costs of this iteration)
         if it == 0:
