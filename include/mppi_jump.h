@@ -237,7 +237,7 @@ int mppi_jump_shift(mppi_jump_ctx* ctx, float* u0_out, void* stream);
  * wave-specialised iteration (mppi_jump_step / mppi_jump_control_step with
  * at most 512 rollout workgroups) holds its tile of perturbations in LDS
  * until the update has used them and never stores them, when the tile fits
- * (the one-channel models with T <= 496; the quadrotor stores its tile);
+ * (T <= 496 for the one-channel models, T <= 108 for the quadrotor);
  * every staged rollout (mppi_jump_rollout), unfused or lane-schedule
  * iteration, batch step and pool tick stores them.  MPPI_ITEM_W and
  * MPPI_ITEM_THRESH are computed at call time (W from the current S and

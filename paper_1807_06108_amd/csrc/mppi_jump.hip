@@ -369,10 +369,10 @@ void bind_context(mppi_jump_ctx* ctx, const mppi_jump_config* cfg, int n, int m,
   ctx->host_iteration = cfg->start_iteration;
 }
 
-// The fused wave-specialised kernel with its perturbation tile on chip (the
-// one-channel models): its dynamic LDS (ring plus tile) can exceed the
-// default launch limit, so the kernel's limit is raised once, to the compute
-// unit's LDS less the static part bounded by kWsStaticLds.
+// The fused wave-specialised kernel with its perturbation tile on chip: its
+// dynamic LDS (ring plus tile) can exceed the default launch limit, so the
+// kernel's limit is raised once, to the compute unit's LDS less the static
+// part bounded by kWsStaticLds.
 template <int DYN, bool JUMPS, int FORM, bool FULL>
 int launch_ws_eps_lds(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, const ShiftArgs& sh) {
   const auto kern = rollout_ws_kernel<DYN, JUMPS, false, FORM, true, FULL, true>;
@@ -391,7 +391,7 @@ int launch_ws_eps_lds(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, const 
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL>
 int launch_rollout_t(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, const ShiftArgs& sh) {
   ctx->eps_stored = !(FUSED && !DEBUG && ctx->L.eps_lds);
-  if constexpr (FUSED && !DEBUG && Model<DYN>::M == 1) {  // one-channel models only
+  if constexpr (FUSED && !DEBUG) {
     if (ctx->L.eps_lds) return launch_ws_eps_lds<DYN, JUMPS, FORM, FULL>(ctx, x0, s, sh);
   }
   if (ctx->L.ws) {

@@ -67,16 +67,24 @@ struct WsConsumeUnroll {
   static constexpr int U = DYN == MPPI_DYN_QUADROTOR ? 4 : kWsChunk;
 };
 
-template <int DYN>
+// Fields of a ring slot, per step and sample: the applied controls v[M]
+// (HAS_V), the body force gust[NG] and the state-free part of the stage
+// cost.  With the perturbation tile on chip (TILE) a multi-channel model's
+// ring omits v: the consumer forms v = U[t] + eps from the tile (the same
+// fp32 sum the producer would form), which shrinks its ring by half so that
+// ring and tile fit in LDS together.
+template <int DYN, bool TILE = false>
 struct WsRing {
   using Md = Model<DYN>;
+  static constexpr bool HAS_V = !(TILE && Md::M > 1);
+  static constexpr int NV = HAS_V ? Md::M : 0;
   static constexpr int NG = Md::JUMP_IN_CONTROL ? 0 : 3;  // disturbance floats
-  static constexpr int NF = Md::M + NG + 1;               // v[M], gust[NG], state-free cost
+  static constexpr int NF = NV + NG + 1;                  // v[NV], gust[NG], state-free cost
 };
 
-template <int DYN>
+template <int DYN, bool TILE = false>
 constexpr size_t ws_ring_bytes() {
-  return sizeof(float) * 2 * kWsChunk * WsRing<DYN>::NF * 64;
+  return sizeof(float) * 2 * kWsChunk * WsRing<DYN, TILE>::NF * 64;
 }
 
 // On-chip perturbation tile of the fused wave-specialised rollout
@@ -85,21 +93,19 @@ constexpr size_t ws_ring_bytes() {
 // read it from there, and the perturbations never go to HBM (eq. (37)'s
 // weights are only known once every cost is, so the tile must be kept until
 // then; on chip it costs neither the store and re-read nor the write-back of
-// the L2 lines that the release fence would otherwise flush).  Used for the
-// one-channel models when the ring and the tile fit beside the kernel's
-// static LDS (T <= 496).  The 12-state model's tile (400 rows at T = 100)
-// and its 16-step ring do not fit together; with 8-step ring slots they do,
-// but measured slower than the HBM round trip (K=8192, T=100: 52.1 against
-// 51.1 us), so it keeps the tile in HBM.
+// the L2 lines that the release fence would otherwise flush).  Used when the
+// ring and the tile fit beside the kernel's static LDS: T <= 496 for the
+// one-channel models, T <= 108 for the 12-state model (whose ring then omits
+// v, above).
 constexpr size_t kLdsBytes = 160 * 1024;     // LDS of a gfx950 compute unit
 constexpr size_t kWsStaticLds = 20 * 1024;   // bound on the kernel's static LDS
 template <int DYN>
 constexpr size_t ws_eps_lds_bytes(int R) {
-  return ws_ring_bytes<DYN>() + sizeof(float) * (size_t)R * kWsSamples;
+  return ws_ring_bytes<DYN, true>() + sizeof(float) * (size_t)R * kWsSamples;
 }
 template <int DYN>
 constexpr bool ws_eps_fits(int R) {
-  return Model<DYN>::M == 1 && ws_eps_lds_bytes<DYN>(R) + kWsStaticLds <= kLdsBytes;
+  return ws_eps_lds_bytes<DYN>(R) + kWsStaticLds <= kLdsBytes;
 }
 
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FULL, bool EPS_LDS>
@@ -107,7 +113,7 @@ __device__ __forceinline__ void ws_produce(const DevParams& p, const Consts& cs,
                                            const float* U, float* slot, float* epsl, int t,
                                            int k, bool active, uint32_t it) {
   using Md = Model<DYN>;
-  using Rg = WsRing<DYN>;
+  using Rg = WsRing<DYN, EPS_LDS>;
   constexpr int M = Md::M, Q = Md::Q;
   Noise<DYN, JUMPS> nz;
   draw_noise<DYN, JUMPS, FULL>(nz, p, cs, (uint32_t)t, p.k0 + (uint32_t)k, it);
@@ -115,10 +121,12 @@ __device__ __forceinline__ void ws_produce(const DevParams& p, const Consts& cs,
 #pragma unroll
   for (int j = 0; j < M; ++j) u[j] = U[t * M + j];
   const int lane = threadIdx.x & 63;
+  if constexpr (Rg::HAS_V) {
 #pragma unroll
-  for (int j = 0; j < M; ++j) slot[j * 64 + lane] = u[j] + nz.eps[j];
+    for (int j = 0; j < M; ++j) slot[j * 64 + lane] = u[j] + nz.eps[j];
+  }
 #pragma unroll
-  for (int i = 0; i < Rg::NG; ++i) slot[(M + i) * 64 + lane] = nz.gust[i];
+  for (int i = 0; i < Rg::NG; ++i) slot[(Rg::NV + i) * 64 + lane] = nz.gust[i];
   slot[(Rg::NF - 1) * 64 + lane] = state_free_cost<M, FORM, FULL>(p, cs, u, nz.eps);
   if constexpr (EPS_LDS) {
 #pragma unroll
@@ -183,43 +191,52 @@ struct WsSlot {
   float v[Model<DYN>::M], gust[3], pre;
 };
 
-template <int DYN>
-__device__ __forceinline__ WsSlot<DYN> ws_read(const float* slot) {
-  using Rg = WsRing<DYN>;
+// The values of step t from its ring slot; without v in the ring, v = U[t] +
+// eps[t] from the on-chip tile.
+template <int DYN, bool TILE>
+__device__ __forceinline__ WsSlot<DYN> ws_read(const float* slot, const float* epsl,
+                                               const float* U, int t) {
+  using Rg = WsRing<DYN, TILE>;
   constexpr int M = Model<DYN>::M;
   const int lane = threadIdx.x & 63;
   WsSlot<DYN> o;
+  if constexpr (Rg::HAS_V) {
 #pragma unroll
-  for (int j = 0; j < M; ++j) o.v[j] = slot[j * 64 + lane];
+    for (int j = 0; j < M; ++j) o.v[j] = slot[j * 64 + lane];
+  } else {
+#pragma unroll
+    for (int j = 0; j < M; ++j) o.v[j] = U[t * M + j] + epsl[(t * M + j) * kWsSamples + lane];
+  }
   o.gust[0] = o.gust[1] = o.gust[2] = 0.f;
 #pragma unroll
-  for (int i = 0; i < Rg::NG; ++i) o.gust[i] = slot[(M + i) * 64 + lane];
+  for (int i = 0; i < Rg::NG; ++i) o.gust[i] = slot[(Rg::NV + i) * 64 + lane];
   o.pre = slot[(Rg::NF - 1) * 64 + lane];
   return o;
 }
 
-// The n steps of a chunk.  For the one-channel models each slot is read one
-// step ahead, so that the LDS latency hides behind the previous step's
-// recursion (their step is short enough for the compiler's own placement to
-// leave it exposed: C1 19.0 -> 18.8 us); the 12-state model reads each slot
-// at its step (reading ahead measured slower there: K=8192 50.7 -> 52.2 us).
-template <int DYN, int UNROLL>
+// The n steps of a chunk starting at step t0.  For the one-channel models
+// each slot is read one step ahead, so that the LDS latency hides behind the
+// previous step's recursion (their step is short enough for the compiler's
+// own placement to leave it exposed: C1 19.0 -> 18.8 us); the 12-state model
+// reads each slot at its step (reading ahead measured slower there: K=8192
+// 50.7 -> 52.2 us).
+template <int DYN, int UNROLL, bool TILE>
 __device__ __forceinline__ void ws_consume_chunk(const DevParams& p, const Consts& cs,
                                                  WsState<DYN>& st, const float* buf, int slot_floats,
-                                                 int n) {
+                                                 int n, int t0, const float* epsl, const float* U) {
   if constexpr (Model<DYN>::M == 1) {
-    WsSlot<DYN> cur = ws_read<DYN>(buf);
+    WsSlot<DYN> cur = ws_read<DYN, TILE>(buf, epsl, U, t0);
 #pragma unroll UNROLL
     for (int s = 0; s < n; ++s) {
       WsSlot<DYN> nxt = cur;
-      if (s + 1 < n) nxt = ws_read<DYN>(buf + (s + 1) * slot_floats);
+      if (s + 1 < n) nxt = ws_read<DYN, TILE>(buf + (s + 1) * slot_floats, epsl, U, t0 + s + 1);
       ws_step<DYN>(p, cs, st, cur.v, cur.gust, cur.pre);
       cur = nxt;
     }
   } else {
 #pragma unroll UNROLL
     for (int s = 0; s < n; ++s) {
-      const WsSlot<DYN> cur = ws_read<DYN>(buf + s * slot_floats);
+      const WsSlot<DYN> cur = ws_read<DYN, TILE>(buf + s * slot_floats, epsl, U, t0 + s);
       ws_step<DYN>(p, cs, st, cur.v, cur.gust, cur.pre);
     }
   }
@@ -233,15 +250,15 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
                                                 const float* U, int R,
                                                 const ShiftArgs& sh, int wg, int nwg) {
   using Md = Model<DYN>;
-  using Rg = WsRing<DYN>;
+  using Rg = WsRing<DYN, EPS_LDS>;
   constexpr int N = Md::N;
   static_assert(!EPS_LDS || FUSED, "the on-chip tile serves the fused epilogue");
   constexpr int NP = W - 1;  // producer waves
   constexpr int CH = kWsChunk;
   constexpr int SLOT = Rg::NF * 64;  // floats per (step) slot
-  // the ring lives in dynamic LDS (ws_ring_bytes<DYN>() at launch, plus the
-  // perturbation tile with EPS_LDS), so that kernels containing several
-  // model variants share one allocation
+  // the ring lives in dynamic LDS (ws_ring_bytes<DYN, EPS_LDS>() at launch,
+  // plus the perturbation tile with EPS_LDS), so that kernels containing
+  // several model variants share one allocation
   extern __shared__ float ws_dyn_lds[];
   float(*ring)[CH][SLOT] = reinterpret_cast<float(*)[CH][SLOT]>(ws_dyn_lds);
   float* epsl = ws_dyn_lds + 2 * CH * SLOT;
@@ -299,9 +316,9 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
     for (int cc = 0; cc < nch; ++cc) {
       float(*buf)[SLOT] = ring[cc & 1];
       if ((cc + 1) * CH <= T)
-        ws_consume_chunk<DYN, kUnroll>(p, cs, st, buf[0], SLOT, CH);
+        ws_consume_chunk<DYN, kUnroll, EPS_LDS>(p, cs, st, buf[0], SLOT, CH, cc * CH, epsl, U);
       else
-        ws_consume_chunk<DYN, 1>(p, cs, st, buf[0], SLOT, T - cc * CH);
+        ws_consume_chunk<DYN, 1, EPS_LDS>(p, cs, st, buf[0], SLOT, T - cc * CH, cc * CH, epsl, U);
       st.S.close_block();  // a chunk is one cost block
       __syncthreads();
     }
