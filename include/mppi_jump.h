@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define MPPI_JUMP_ABI_VERSION 3
+#define MPPI_JUMP_ABI_VERSION 4
 
 #define MPPI_JUMP_MAX_N 12      /* state dimension bound            */
 #define MPPI_JUMP_MAX_M 4       /* control dimension bound          */
@@ -63,6 +63,10 @@ extern "C" {
 /* jump count law (Sec. IV-B): Poisson(nu dt) or the zero-one law */
 #define MPPI_COUNT_POISSON 0
 #define MPPI_COUNT_ZERO_ONE 1
+
+/* jump-mark law (Sec. II: the marks of the compound-Poisson process are
+ * normal, N(0, diag sigma_J^2) per jump) */
+#define MPPI_MARK_NORMAL 0
 
 /* path-cost form: information-theoretic (eqs. (34)-(35), with the
  * importance-sampling terms) or stochastic-optimisation (Sec. IV: cost on the
@@ -131,6 +135,7 @@ typedef struct mppi_jump_config {
                             sample k draws the noise of sample_offset + k, so
                             controllers with disjoint offsets are shards of
                             one larger sample set; >= 0, offset + K <= 2^31  */
+  int32_t mark_law;      /* MPPI_MARK_*: distribution of a jump's mark          */
 } mppi_jump_config;
 /* params: cartpole  = {m_cart, m_pole, half_length, g}
  *         quadrotor = {mass, Jx, Jy, Jz, arm, k_yaw, g, tilt_max, z_min}

@@ -122,6 +122,7 @@ int validate(const mppi_jump_config* c, int& n, int& m, int& q, Thresholds& th) 
   if (!(std::isfinite(c->nu) && c->nu >= 0.f)) return fail(MPPI_EINVAL, "nu must be finite and >= 0");
   if (c->count_law != MPPI_COUNT_POISSON && c->count_law != MPPI_COUNT_ZERO_ONE)
     return fail(MPPI_EINVAL, "unknown count_law %d", c->count_law);
+  if (c->mark_law != MPPI_MARK_NORMAL) return fail(MPPI_EINVAL, "unknown mark_law %d", c->mark_law);
   if (c->cost_form != MPPI_COST_IT && c->cost_form != MPPI_COST_SO)
     return fail(MPPI_EINVAL, "unknown cost_form %d", c->cost_form);
   if (c->debug_dump != 0 && c->debug_dump != 1) return fail(MPPI_EINVAL, "debug_dump must be 0 or 1");

@@ -56,7 +56,7 @@ class Config(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("controller_id", ctypes.c_uint64),
         ("start_iteration", ctypes.c_uint64),
         ("full_sigma", ctypes.c_int32), ("sigma_L", ctypes.c_float * 16),
-        ("sample_offset", ctypes.c_int32),
+        ("sample_offset", ctypes.c_int32), ("mark_law", ctypes.c_int32),
     ]
 
 

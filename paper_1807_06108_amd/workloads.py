@@ -46,7 +46,7 @@ def base_config(dynamics):
                 u_init=[0.0] * 4, R=[0.0] * 4, Q=[0.0] * 12, Qf=[0.0] * 12,
                 x_goal=[0.0] * 12, params=[0.0] * 12, crash_penalty=0.0, schedule=0,
                 seed=DEFAULT_SEED, controller_id=0, start_iteration=0,
-                full_sigma=0, sigma_L=[0.0] * 16, sample_offset=0)
+                full_sigma=0, sigma_L=[0.0] * 16, sample_offset=0, mark_law=0)
 
 
 def random_cholesky(m, scale, seed):

@@ -113,6 +113,11 @@ def test_abi_version_mismatch_and_jump_table_overflow():
     q["params"][7] = 1.6
     with pytest.raises(native.MppiError):
         native.workspace_bytes(q)
+    # the jump marks are normal (the only law the configuration names)
+    with pytest.raises(native.MppiError) as e:
+        native.workspace_bytes(workloads.cartpole(mark_law=1))
+    assert e.value.code == native.C["MPPI_EINVAL"] and "mark_law" in str(e.value)
+    assert native.C["MPPI_MARK_NORMAL"] == 0
 
 
 @pytest.mark.parametrize("nu,law,dt", [(0.0, 0, 0.02), (2.0, 0, 0.02), (5.0, 0, 0.02),
