@@ -23,6 +23,9 @@ The JSON line also carries
                    MPC-step requests/s: p50/p99 latency (arrival to u0 on the
                    host) of pooled ticks against per-controller launches, and
                    the capacity of each back end,
+  saturation       the same rollout at a shape that fills the GPU (K=2^20,
+                   lane schedule) per model: the kernel against its roofline
+                   where occupancy does not bound it,
   other_configs    the other single-GPU configurations, each with its value,
                    time per iteration, roofline and oracle timings: the single
                    cartpole iteration (K=256, T=50) and the quadrotor hover
@@ -234,16 +237,16 @@ def cpu_baseline_all_cores(cfg, x0, U0, iters, dist, budget_s, pool, workers):
                        % (steps, cfg["K"], workers, el))
 
 
-def iteration_measure(name, calls, warmup):
-    """One plain-form controller of a preset single-iteration workload: `calls`
-    iterations (one fused launch each, the rollout kernel timed by HIP events
-    on its stream around every launch) from the preset state, each from the
-    previous one's sequence.  Returns the workload's sub-object of the line
-    (its cpu_baseline legs are added by the caller)."""
+def iteration_measure(name, calls, warmup, **over):
+    """One plain-form controller of a preset single-iteration workload
+    (fields overridden by `over`): `calls` iterations (the rollout kernel
+    timed by HIP events on its stream around every launch) from the preset
+    state, each from the previous one's sequence.  Returns the workload's
+    sub-object of the line (its cpu_baseline legs are added by the caller)."""
     import torch
     from paper_1807_06108_amd import workloads
     from paper_1807_06108_amd.controller import Controller
-    cfg = workloads.PRESETS[name]()
+    cfg = workloads.PRESETS[name](**over)
     K, T, dyn = cfg["K"], cfg["T"], cfg["dynamics"]
     ctl = Controller(cfg, workloads.U0_for(cfg))
     x = torch.tensor(workloads.x0_for(cfg), device="cuda")
@@ -262,13 +265,14 @@ def iteration_measure(name, calls, warmup):
     achieved = ALG_SLOTS[dyn] * K * T / avg_roll_s
     flops = ALG_FP32_FLOP[dyn] * K * T / avg_roll_s
     return {"workload": name, "K": K, "T": T, "dt": cfg["dt"], "dynamics": dyn, "nu": cfg["nu"],
+            "schedule": {0: "auto", 1: "lane", 2: "ws"}[cfg.get("schedule", 0)],
             "iterations": calls, "value": K * T * calls / wall, "unit": "rollout-steps/s",
             "ms_per_iteration": wall / calls * 1e3,
             "roofline": {"bound": "alu",
                          "kernel": "rollout (sampling, propagation, cost, weights, update)",
                          "achieved": achieved / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
                          "unit": "T VALU-slot/s", "frac": achieved / VALU_PEAK_SLOTS,
-                         "traffic": measured_traffic(name),
+                         "traffic": measured_traffic(name) if not over else None,
                          "avg_launch_us": avg_roll_s * 1e6, "launches_timed": launches,
                          "slots_per_sample_step": ALG_SLOTS[dyn],
                          "fp32_tflops": flops / 1e12, "fp32_frac": flops / FP32_PEAK}}
@@ -354,12 +358,12 @@ def serving_measure(rate, seconds, warm, n_ctl=1024, seed=4):
     sched, report = autotune.choose_schedule(
         cfgs, [torch.tensor(x, device="cuda") for x in x0s], subset=4)
 
-    def run(backend, schedule, r, secs, w):
+    def run(backend, schedule, r, secs, w, cap=64 << 30):
         t, ids = workloads.serving_arrivals(r, secs + w, n_ctl, seed=9)
-        srv = serving.Server(cfgs, x0s, dist, hbm_cap_bytes=64 << 30, max_inflight=4,
+        srv = serving.Server(cfgs, x0s, dist, hbm_cap_bytes=cap, max_inflight=4,
                              backend=backend, schedule=schedule)
         res = srv.run(t, ids, warmup_s=w)
-        res.update(admitted=len(srv.admitted), admitted_gb=srv.admitted_bytes / 2**30)
+        res.update(admitted=len(srv.admitted), resident_gb_at_end=srv.resident_bytes / 2**30)
         srv.close()
         torch.cuda.synchronize()
         return res
@@ -372,6 +376,18 @@ def serving_measure(rate, seconds, warm, n_ctl=1024, seed=4):
     progress("serving: per-controller launches at %.0f requests/s" % rate)
     out["plain"] = run("plain", sched, rate, seconds, warm)
     out["p99_ratio_plain_over_pool"] = out["plain"]["latency_ms"]["p99"] / out["pool"]["latency_ms"]["p99"]
+    # a cap that holds about a quarter of the controllers' workspaces:
+    # requests wait for admission, idle residents are evicted (state saved on
+    # the host) and rebuilt on their next request.  Three quarters of the
+    # requests then need an admission, which is host work, so the offered
+    # rate is a tenth of the one above.
+    total = sum(serving.footprint_bytes(c) for c in cfgs)
+    bounded, b_rate, b_secs = total // 4, rate / 10, min(seconds, 3.0)
+    progress("serving: pooled ticks under a %.2f GiB residency cap, %.0f requests/s"
+             % (bounded / 2**30, b_rate))
+    out["pool_bounded"] = dict(run("pool", sched, b_rate, b_secs, 1.0, cap=bounded),
+                               offered_per_s=b_rate, hbm_cap_gb=bounded / 2**30,
+                               workspaces_gb=total / 2**30)
     cap = {}
     for name, backend, schedule, offered in (("pool_lane", "pool", 1, 250e3),
                                              ("pool_ws", "pool", 2, 250e3),
@@ -463,6 +479,9 @@ def main():
     ap.add_argument("--iteration-calls", type=int, default=300,
                     help="iterations timed on each other single-GPU configuration "
                          "(cartpole K=256 T=50, quadrotor K=8192 T=100); 0 skips them")
+    ap.add_argument("--saturation-calls", type=int, default=10,
+                    help="iterations timed at the saturating shape K=2^20 (lane schedule) of "
+                         "each model; 0 skips them")
     ap.add_argument("--cpu-workers", type=int, default=None,
                     help="worker processes of the all-cores oracle timing (default: the "
                          "usable host cores, at most 16; 0 skips it)")
@@ -604,7 +623,7 @@ def main():
         progress("batched form")
         line["batched"] = batched_measure(args.batched_controllers, args.batched_ticks, 3)
     if args.serving_seconds > 0:
-        progress("serving form (about %.0f s)" % (2 * (args.serving_seconds + args.serving_warmup) + 5))
+        progress("serving form (about %.0f s)" % (2 * (args.serving_seconds + args.serving_warmup) + 15))
         line["serving"] = serving_measure(args.serving_rate, args.serving_seconds,
                                           args.serving_warmup)
     # the other single-GPU configurations: the single cartpole iteration
@@ -616,6 +635,15 @@ def main():
                 progress("plain form: %s" % name)
                 others.append(iteration_measure(name, args.iteration_calls, 20))
         line["other_configs"] = others
+    # saturating shapes: one controller of 2^20 samples (4096 lane-schedule
+    # workgroups fill every compute unit several times over; the update then
+    # runs as its own HBM-bound kernel), per model
+    if args.saturation_calls > 0 and args.K is None and args.T is None:
+        line["saturation"] = []
+        for name in ("cartpole_mpc", "quadrotor_hover"):
+            progress("saturating shape: %s, K=2^20" % name)
+            line["saturation"].append(iteration_measure(name, args.saturation_calls, 2,
+                                                        K=1 << 20, schedule=1))
     if not args.no_cpu_baseline:
         progress("oracle on one host core (about %.0f s)" % args.cpu_budget)
         line["cpu_baseline"] = cpu_baseline(cfg, x0, U0, iters,

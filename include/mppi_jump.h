@@ -364,6 +364,16 @@ int mppi_jump_pool_tick(mppi_jump_pool* pool, const int32_t* ids, const float* s
                         const float* dist, int32_t count, int32_t iters, int32_t slot,
                         void* stream);
 
+/* Put ctx at position `index` of the pool in place of its context, so that
+ * a pool of fixed size can hold a changing set of resident controllers (a
+ * server admitting a controller in place of one it evicted).  ctx must meet
+ * the conditions of the pool's contexts (same rollout schedule; fused
+ * update; no debug_dump; diagonal covariance); the position must not be in a
+ * tick in flight (EINVAL).  Uploads the position's descriptor on `stream`
+ * and synchronises it, so later ticks on any stream see the new context.
+ * The caller keeps ctx and its workspace alive while the pool holds it. */
+int mppi_jump_pool_replace(mppi_jump_pool* pool, int32_t index, mppi_jump_ctx* ctx, void* stream);
+
 /* *finished = 1 when the slot holds no tick or its tick has finished on the
  * device, else 0.  Does not block. */
 int mppi_jump_pool_query(mppi_jump_pool* pool, int32_t slot, int32_t* finished);
@@ -387,6 +397,12 @@ int mppi_jump_pool_destroy(mppi_jump_pool* pool);
  * control).  One GPU thread. */
 int mppi_jump_plant_step(mppi_jump_ctx* ctx, float* d_x, const float* d_u,
                          const float* d_dist, void* stream);
+
+/* The same plant step with a world-frame body force d_force ([3] fp32
+ * device; NULL = none) for the models that take one (the quadrotor's gust;
+ * the others ignore it), as the pool's plant step applies it. */
+int mppi_jump_plant_step_force(mppi_jump_ctx* ctx, float* d_x, const float* d_u,
+                               const float* d_dist, const float* d_force, void* stream);
 
 /* Philox4x32-10 blocks of the library's generator for n caller-given
  * counters: d_out[4i..4i+4) = Philox(d_counters[4i..4i+4), key).  For

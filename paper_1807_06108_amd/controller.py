@@ -119,9 +119,11 @@ class Controller:
         self._publish()
         return out
 
-    def plant_step(self, x, u, d):
-        """Simulated plant: x <- Euler(x, u + d) on device tensors."""
-        native.check(native.lib().mppi_jump_plant_step(self.ctx, _ptr(x), _ptr(u), _ptr(d), self._s()))
+    def plant_step(self, x, u, d, force=None):
+        """Simulated plant: x <- Euler(x, u + d) on device tensors, with the
+        world-frame body force `force` ([3], quadrotor) if given."""
+        native.check(native.lib().mppi_jump_plant_step_force(self.ctx, _ptr(x), _ptr(u), _ptr(d),
+                                                             _ptr(force), self._s()))
         self._publish()
 
     # ------------------------------------------------------------- items
@@ -305,6 +307,13 @@ class Pool:
                                                       _np_ptr(dist), len(ids), int(iters),
                                                       int(slot), _stream_handle(stream)))
         self._count[slot] = len(ids)
+
+    def replace(self, index, controller, stream=None):
+        """Put `controller` at pool position `index` (not in a tick in flight)
+        in place of the controller there; synchronises `stream`."""
+        native.check(native.lib().mppi_jump_pool_replace(self.pl, int(index), controller.ctx,
+                                                         _stream_handle(stream)))
+        self.controllers[index] = controller
 
     def finished(self, slot):
         f = ctypes.c_int32()

@@ -784,13 +784,21 @@ __global__ __launch_bounds__(1024) void shift_kernel(float* __restrict__ U, int 
   }
 }
 
+// One explicit Euler step of the plant under u + d and, for the models that
+// take one, the world-frame body force (null: none).
 template <int DYN>
 __global__ void plant_kernel(const DevParams p, float* __restrict__ x,
-                             const float* __restrict__ u, const float* __restrict__ d) {
+                             const float* __restrict__ u, const float* __restrict__ d,
+                             const float* __restrict__ force) {
   using Md = Model<DYN>;
   if (blockIdx.x != 0 || threadIdx.x != 0) return;
   float s[Md::N], v[Md::M];
-  const float gust[3] = {0.f, 0.f, 0.f};
+  float gust[3] = {0.f, 0.f, 0.f};
+  if (force != nullptr) {
+    gust[0] = force[0];
+    gust[1] = force[1];
+    gust[2] = force[2];
+  }
 #pragma unroll
   for (int i = 0; i < Md::N; ++i) s[i] = x[i];
 #pragma unroll

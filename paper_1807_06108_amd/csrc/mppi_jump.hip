@@ -1193,13 +1193,12 @@ int mppi_jump_pool_create(mppi_jump_ctx* const* ctxs, int32_t n, int32_t max_inf
       d.form = c->cfg.cost_form;
       d.m = c->m;
       pl->cost[i] = tile_cost(c);
-      if (pl->ws) {
-        const size_t lds = c->cfg.dynamics == MPPI_DYN_QUADROTOR ? ws_ring_bytes<MPPI_DYN_QUADROTOR>()
-                           : c->cfg.dynamics == MPPI_DYN_CARTPOLE ? ws_ring_bytes<MPPI_DYN_CARTPOLE>()
-                                                                  : ws_ring_bytes<MPPI_DYN_LINEAR>();
-        if (lds > pl->dyn_lds) pl->dyn_lds = lds;
-      }
     }
+    // a wave-specialised pool launches with the largest ring of any model, so
+    // that a position can take a context of any model (mppi_jump_pool_replace)
+    if (pl->ws)
+      pl->dyn_lds = std::max({ws_ring_bytes<MPPI_DYN_QUADROTOR>(), ws_ring_bytes<MPPI_DYN_CARTPOLE>(),
+                              ws_ring_bytes<MPPI_DYN_LINEAR>()});
     // the staging is zeroed once so that unused state / disturbance words
     // of a request are defined
     std::memset(pl->h_slots, 0, need_h);
@@ -1314,6 +1313,37 @@ int mppi_jump_pool_tick(mppi_jump_pool* pl, const int32_t* ids, const float* sta
   });
 }
 
+int mppi_jump_pool_replace(mppi_jump_pool* pl, int32_t index, mppi_jump_ctx* ctx, void* stream) {
+  return guarded([&]() -> int {
+    if (!pl || !ctx) return fail(MPPI_EINVAL, "NULL argument");
+    if (index < 0 || index >= pl->n) return fail(MPPI_EINVAL, "index %d out of [0, %d)", index, pl->n);
+    if (pl->busy[index] >= 0) return fail(MPPI_EINVAL, "position %d is in a tick in flight", index);
+    BatchLayout BL;
+    bool ws = false;
+    mppi_jump_ctx* one[1] = {ctx};
+    const int rc = batch_check(one, 1, BL, ws);
+    if (rc != MPPI_OK) return rc;
+    if (ws != pl->ws) return fail(MPPI_EINVAL, "the context's rollout schedule differs from the pool's");
+    BatchDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.p = ctx->p;
+    d.b = ctx->b;
+    d.u_init = u_init4(ctx->cfg);
+    d.R = ctx->L.R;
+    d.nwg = ctx->L.nwg;
+    d.dyn = ctx->cfg.dynamics;
+    d.jumps = ctx->p.n_th > 0 ? 1 : 0;
+    d.form = ctx->cfg.cost_form;
+    d.m = ctx->m;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipMemcpyAsync(pl->d_desc + index, &d, sizeof d, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    pl->ctxs[index] = ctx;
+    pl->cost[index] = tile_cost(ctx);
+    return ok();
+  });
+}
+
 int mppi_jump_pool_query(mppi_jump_pool* pl, int32_t slot, int32_t* finished) {
   return guarded([&]() -> int {
     if (!pl || !finished) return fail(MPPI_EINVAL, "NULL argument");
@@ -1387,19 +1417,30 @@ const char* mppi_jump_strerror(int code) {
 
 const char* mppi_jump_last_error(void) { return g_last_error; }
 
-int mppi_jump_plant_step(mppi_jump_ctx* ctx, float* d_x, const float* d_u, const float* d_dist,
-                         void* stream) {
+int mppi_jump_plant_step_force(mppi_jump_ctx* ctx, float* d_x, const float* d_u,
+                               const float* d_dist, const float* d_force, void* stream) {
   return guarded([&]() -> int {
     if (!ctx || !d_x || !d_u || !d_dist) return fail(MPPI_EINVAL, "NULL argument");
     const hipStream_t s = static_cast<hipStream_t>(stream);
     switch (ctx->cfg.dynamics) {
-      case MPPI_DYN_LINEAR: plant_kernel<MPPI_DYN_LINEAR><<<1, 64, 0, s>>>(ctx->p, d_x, d_u, d_dist); break;
-      case MPPI_DYN_CARTPOLE: plant_kernel<MPPI_DYN_CARTPOLE><<<1, 64, 0, s>>>(ctx->p, d_x, d_u, d_dist); break;
-      default: plant_kernel<MPPI_DYN_QUADROTOR><<<1, 64, 0, s>>>(ctx->p, d_x, d_u, d_dist); break;
+      case MPPI_DYN_LINEAR:
+        plant_kernel<MPPI_DYN_LINEAR><<<1, 64, 0, s>>>(ctx->p, d_x, d_u, d_dist, d_force);
+        break;
+      case MPPI_DYN_CARTPOLE:
+        plant_kernel<MPPI_DYN_CARTPOLE><<<1, 64, 0, s>>>(ctx->p, d_x, d_u, d_dist, d_force);
+        break;
+      default:
+        plant_kernel<MPPI_DYN_QUADROTOR><<<1, 64, 0, s>>>(ctx->p, d_x, d_u, d_dist, d_force);
+        break;
     }
     LAUNCH_CHECK("plant_kernel");
     return ok();
   });
+}
+
+int mppi_jump_plant_step(mppi_jump_ctx* ctx, float* d_x, const float* d_u, const float* d_dist,
+                         void* stream) {
+  return mppi_jump_plant_step_force(ctx, d_x, d_u, d_dist, nullptr, stream);
 }
 
 int mppi_jump_philox(const uint32_t* d_counters, uint32_t key0, uint32_t key1, uint32_t* d_out,

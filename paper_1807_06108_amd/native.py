@@ -120,6 +120,7 @@ _PROTOS = {
     "mppi_jump_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "mppi_jump_last_error": (ctypes.c_char_p, []),
     "mppi_jump_plant_step": (ctypes.c_int, [ctypes.c_void_p] * 5),
+    "mppi_jump_plant_step_force": (ctypes.c_int, [ctypes.c_void_p] * 6),
     "mppi_jump_batch_scratch_bytes": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
                                                      ctypes.POINTER(ctypes.c_size_t)]),
     "mppi_jump_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p),
@@ -140,6 +141,8 @@ _PROTOS = {
     "mppi_jump_pool_tick": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                            ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_int32, ctypes.c_void_p]),
+    "mppi_jump_pool_replace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                              ctypes.c_void_p]),
     "mppi_jump_pool_query": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
     "mppi_jump_pool_results": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                               ctypes.c_void_p, ctypes.c_void_p,

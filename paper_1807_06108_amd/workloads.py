@@ -205,19 +205,23 @@ def serving_arrivals(rate, duration, count, seed=9):
 
 
 def serving_disturbances(cfg, steps, seed):
-    """Plant disturbances of one served controller, [steps, 4] fp32, added to
-    its control channels: N(0, sigma_j^2) per channel plus, where the model's
-    jumps enter the control channels, a Poisson(nu dt) number of
-    N(0, sigma_J^2) jumps (one count per step).  The quadrotor's jumps are a
-    world-frame gust, which this plant step does not model, so its plant gets
-    the Gaussian part only."""
+    """Plant disturbances of one served controller, [steps, 8] fp32: words
+    0..3 added to its control channels, N(0, sigma_j^2) per channel plus,
+    where the model's jumps enter the control channels, a Poisson(nu dt)
+    number of N(0, sigma_J^2) jumps (one count per step); words 4..6 the
+    quadrotor's world-frame gust, sqrt(N) N(0, sigma_J^2) per axis with
+    N ~ Poisson(nu dt), held for one step (the plant step applies it as a
+    body force); word 7 unused."""
     n, m, q = DIMS[cfg["dynamics"]]
     g = np.random.default_rng(seed)
     sig = np.asarray(cfg["sigma"][:m], dtype=np.float64)
-    d = np.zeros((steps, 4))
+    d = np.zeros((steps, 8))
     d[:, :m] = sig * g.standard_normal((steps, m))
+    cnt = g.poisson(cfg["nu"] * cfg["dt"], size=steps)
     if cfg["dynamics"] != 2:
-        cnt = g.poisson(cfg["nu"] * cfg["dt"], size=steps)
         sj = np.asarray(cfg["sigma_J"][:m], dtype=np.float64)
         d[:, :m] += sj * np.sqrt(cnt)[:, None] * g.standard_normal((steps, m))
+    else:
+        sj = np.asarray(cfg["sigma_J"][:3], dtype=np.float64)
+        d[:, 4:7] = sj * np.sqrt(cnt)[:, None] * g.standard_normal((steps, 3))
     return d.astype(np.float32)

@@ -157,10 +157,12 @@ def test_serving_workload_recipe():
     gaps = np.diff(t)
     assert abs(gaps.mean() - 5e-5) < 2e-6 and abs(gaps.std() / gaps.mean() - 1.0) < 0.03
     assert t.max() < 2.0 and ids.min() >= 0 and ids.max() < 1024
-    d = workloads.serving_disturbances(workloads.quadrotor(), 1000, seed=1)
-    assert d.shape == (1000, 4) and abs(d.std() - 0.5) < 0.05
+    d = workloads.serving_disturbances(workloads.quadrotor(), 20000, seed=1)
+    assert d.shape == (20000, 8) and abs(d[:, :4].std() - 0.5) < 0.01 and not d[:, 7].any()
+    # the gust: per axis variance nu dt sigma_J^2 = 0.03 * 9
+    assert np.allclose(d[:, 4:7].var(axis=0) / 0.27, 1.0, atol=0.1)
     d = workloads.serving_disturbances(workloads.cartpole_mpc(), 20000, seed=1)
-    assert not d[:, 1:].any()
+    assert d.shape == (20000, 8) and not d[:, 1:].any()
     # variance 1 + nu dt sigma_J^2 = 1 + 0.1 * 100
     assert abs(d[:, 0].var() / 11.0 - 1.0) < 0.1
 
@@ -170,12 +172,12 @@ def test_admission_by_footprint():
     cfgs = [c for c, _ in workloads.serving_controllers(64)]
     need = [serving.footprint_bytes(c) for c in cfgs]
     assert need == [native.workspace_bytes(c) for c in cfgs]
-    ok, refused, used = serving.admit(cfgs, sum(need))
-    assert ok == list(range(64)) and not refused and used == sum(need)
+    ok, rest, used = serving.admit(cfgs, sum(need))
+    assert ok == list(range(64)) and not rest and used == sum(need)
     cap = sum(need[:10]) + 1
-    ok, refused, used = serving.admit(cfgs, cap)
+    ok, rest, used = serving.admit(cfgs, cap)
     assert ok[:10] == list(range(10)) and used <= cap
-    assert sorted(ok + refused) == list(range(64))
+    assert sorted(ok + rest) == list(range(64))
 
 
 def test_study_success_criterion():

@@ -119,7 +119,8 @@ def test_pool_equals_plain_control_step():
             ctl = b_ctl[c]
             x = torch.tensor(st[c, :ctl.n], device="cuda")
             u = ctl.control_step(x, 2)
-            ctl.plant_step(x, u, torch.tensor(d[j, :ctl.m], device="cuda"))
+            ctl.plant_step(x, u, torch.tensor(d[j, :ctl.m], device="cuda"),
+                           torch.tensor(d[j, 4:7], device="cuda"))
             np.testing.assert_array_max_ulp(u0[j, :ctl.m], u.cpu().numpy(), maxulp=1)
             assert not u0[j, ctl.m:].any()
             np.testing.assert_allclose(xn[j, :ctl.n], x.cpu().numpy(), rtol=1e-5, atol=1e-5)
@@ -173,6 +174,19 @@ def test_pool_guards():
     pool.results(1, plant=False)
     with pytest.raises(native.MppiError):
         Pool(ctls, 17)
+    # replacing a position: not while its controller is in flight, not with
+    # another rollout schedule, not out of range
+    spare = Controller(cset[0][0])
+    pool.tick([0], st[[0]], slot=0)
+    assert code(lambda: pool.replace(0, spare)) == EINVAL
+    torch.cuda.synchronize()
+    pool.results(0, plant=False)
+    assert code(lambda: pool.replace(len(ctls), spare)) == EINVAL
+    assert code(lambda: pool.replace(1, Controller(dict(cset[1][0], schedule=WS)))) == EINVAL
+    pool.replace(0, spare)
+    pool.tick([0, 2], st[[0, 2]], slot=1)
+    torch.cuda.synchronize()
+    assert list(pool.results(1, plant=False)[0]) == [0, 2]
 
 
 def test_server_serves_every_request_with_both_back_ends():
@@ -189,18 +203,37 @@ def test_server_serves_every_request_with_both_back_ends():
         assert r["requests"] == len(t)
         assert np.array_equal(srv.served, counts)
         assert r["latency_ms"]["p50"] > 0
-        for i, ctl in enumerate(srv.controllers):
-            if counts[i]:
-                assert ctl.stats()["iteration"] == cfgs[i]["start_iteration"] + counts[i]
+        for i in range(len(cfgs)):
+            assert srv.iteration(i) == cfgs[i]["start_iteration"] + counts[i]
         srv.close()
 
 
-def test_admission_refuses_beyond_the_cap():
-    cset = _set(WS, n=6, seed=31)
+@pytest.mark.parametrize("backend", ["pool", "plain"])
+def test_bounded_residency_gives_the_same_results(backend):
+    """Under an HBM cap that holds two or three of the controllers, requests
+    wait for admission and idle residents are evicted and later rebuilt from
+    their saved control sequence and iteration counter: every request's u_0
+    and every plant state are bitwise those of a server with every
+    controller resident."""
+    cset = _set(WS, n=9, seed=31)
     cfgs = [c for c, _ in cset]
-    need = [serving.footprint_bytes(c) for c in cfgs]
-    cap = sum(need[:3]) + need[3] // 2
-    srv = serving.Server(cfgs, [x for _, x in cset], _dists(cset), hbm_cap_bytes=cap)
-    assert srv.admitted[:3] == [0, 1, 2] and 3 in srv.refused
-    assert srv.admitted_bytes <= cap
-    srv.close()
+    x0s = [x for _, x in cset]
+    dist = _dists(cset, steps=16)
+    need = sorted(serving.footprint_bytes(c) for c in cfgs)
+    cap = need[-1] + need[len(need) // 2]
+    t, ids = workloads.serving_arrivals(rate=1500.0, duration=0.12, count=len(cset), seed=4)
+    print("bounded residency", backend, len(t), "requests, cap", cap, flush=True)
+    ref = serving.Server(cfgs, x0s, dist, max_inflight=2, backend=backend)
+    ref.run(t, ids, record=True)
+    srv = serving.Server(cfgs, x0s, dist, hbm_cap_bytes=cap, max_inflight=2, backend=backend)
+    r = srv.run(t, ids, record=True)
+    assert r["requests"] == len(t) and srv.evictions > 0 and srv.resident_bytes <= cap
+    assert np.array_equal(srv.served, np.bincount(ids, minlength=len(cset)))
+    for c in range(len(cset)):
+        assert len(srv.log[c]) == len(ref.log[c])
+        for a, b in zip(srv.log[c], ref.log[c]):
+            assert np.array_equal(a, b), c
+        assert srv.iteration(c) == ref.iteration(c)
+    assert np.array_equal(srv.state, ref.state)
+    for s in (ref, srv):
+        s.close()
