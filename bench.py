@@ -67,6 +67,9 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rollout_traffic.json")
 
 
 # sources that define the plain rollout kernels and their launch
+# the rollout kernels: one iteration per launch, or a control step's
+# iterations in one launch
+DOMINANT_KERNELS = ("void mppi::rollout", "void mppi::control_step")
 KERNEL_SOURCES = ("kernels.hpp", "rollout_ws.hpp", "rng.hpp", "models.hpp", "reduce.hpp",
                   "mppi_jump.hip")
 
@@ -260,7 +263,7 @@ def iteration_measure(name, calls, warmup, **over):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ctl.profile(False)
-    roll_ms, launches = ctl.profile_read()
+    roll_ms, launches, _ = ctl.profile_read()
     avg_roll_s = roll_ms / launches * 1e-3
     achieved = ALG_SLOTS[dyn] * K * T / avg_roll_s
     flops = ALG_FP32_FLOP[dyn] * K * T / avg_roll_s
@@ -402,7 +405,8 @@ def serving_measure(rate, seconds, warm, n_ctl=1024, seed=4):
 
 def counter_per_dispatch(csv_dir, counter, kernel_prefix):
     """(mean value per dispatch, dispatches) of one rocprofv3 counter over
-    the dispatches of kernels whose name starts with kernel_prefix, from the
+    the dispatches of kernels whose name starts with kernel_prefix (a string
+    or a tuple of them), from the
     *counter_collection.csv files under csv_dir."""
     import csv
     import glob
@@ -442,9 +446,9 @@ def traffic_summary(pmc_dir, workloads):
            "workloads": {}}
     for w in workloads:
         f, nf = counter_per_dispatch(os.path.join(pmc_dir, "FETCH_SIZE_" + w), "FETCH_SIZE",
-                                     "void mppi::rollout")
+                                     DOMINANT_KERNELS)
         wr, nw = counter_per_dispatch(os.path.join(pmc_dir, "WRITE_SIZE_" + w), "WRITE_SIZE",
-                                      "void mppi::rollout")
+                                      DOMINANT_KERNELS)
         out["workloads"][w] = {"FETCH_SIZE_kib": f, "WRITE_SIZE_kib": wr, "dispatches": [nf, nw],
                                "bytes_per_launch": 1024 * (f * fetch_scale + wr * write_scale)}
     return out
@@ -560,7 +564,7 @@ def main():
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    roll_ms, launches = ctl.profile_read()
+    roll_ms, launches, roll_iters = ctl.profile_read()
     lat = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)])
 
     # host in the loop: state uploaded, control step, u0 downloaded (timed);
@@ -581,9 +585,13 @@ def main():
         x_host.copy_(x)
 
     value = K * T * iters * args.steps / wall
+    # the dominant kernel: one launch per control step (all its iterations)
+    # or one per iteration; its algorithmic work per launch is that of the
+    # iterations it runs
     avg_roll_s = roll_ms / launches * 1e-3
-    achieved = ALG_SLOTS[dyn] * K * T / avg_roll_s
-    flops = ALG_FP32_FLOP[dyn] * K * T / avg_roll_s
+    per_launch = roll_iters / launches
+    achieved = ALG_SLOTS[dyn] * K * T * per_launch / avg_roll_s
+    flops = ALG_FP32_FLOP[dyn] * K * T * per_launch / avg_roll_s
     line = {
         "metric": "rollout-steps/sec (K*T*iters) + p99 MPC-step latency, plain "
                   "per-controller launch",
@@ -609,12 +617,16 @@ def main():
                           "what": "state host->device, control step, u0 device->host, "
                                   "synchronise"} if host_lat else None),
         "roofline": {"bound": "alu",
-                     "kernel": "rollout (sampling, propagation, cost, weights, update)",
+                     "kernel": ("control step, %d iterations in one launch (sampling, "
+                                "propagation, cost, weights, update, shift)" % per_launch
+                                if per_launch > 1 else
+                                "rollout (sampling, propagation, cost, weights, update)"),
                      "achieved": achieved / 1e12, "peak": VALU_PEAK_SLOTS / 1e12,
                      "unit": "T VALU-slot/s", "frac": achieved / VALU_PEAK_SLOTS,
                      "traffic": (measured_traffic(args.workload)
                                  if args.K is None and args.T is None else None),
                      "avg_launch_us": avg_roll_s * 1e6, "launches_timed": launches,
+                     "iterations_per_launch": per_launch,
                      "slots_per_sample_step": ALG_SLOTS[dyn],
                      "fp32_tflops": flops / 1e12, "fp32_frac": flops / FP32_PEAK},
     }

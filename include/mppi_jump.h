@@ -197,6 +197,7 @@ int mppi_jump_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, void* s
 int mppi_jump_control_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters,
                            float* d_u0_out, void* stream);
 
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): one MPC
  * control step exactly as mppi_jump_control_step (same kernels, same
@@ -413,12 +414,14 @@ int mppi_jump_philox(const uint32_t* d_counters, uint32_t key0, uint32_t key1,
 /* Timing of the rollout kernel: when enabled, rollout launches are bracketed
  * by HIP events on their stream: the fused launches of one mppi_jump_step /
  * mppi_jump_control_step call (back-to-back rollout kernels) by one event
- * pair, any other rollout launch by its own.  profile_read synchronises on
- * the recorded events and returns the summed bracketed duration (ms) and the
- * number of rollout launches inside the brackets, then clears them.  At most
- * 4096 brackets are kept. */
+ * pair, any other rollout launch by its own.
+ * profile_read synchronises on the recorded events and returns the summed
+ * bracketed duration (ms), the number of rollout launches and the number of
+ * iterations inside the brackets, then clears them.  At most 4096 brackets
+ * are kept. */
 int mppi_jump_profile(mppi_jump_ctx* ctx, int32_t enable);
-int mppi_jump_profile_read(mppi_jump_ctx* ctx, double* total_ms, int64_t* launches);
+int mppi_jump_profile_read(mppi_jump_ctx* ctx, double* total_ms, int64_t* launches,
+                           int64_t* iterations);
 
 #ifdef __cplusplus
 }

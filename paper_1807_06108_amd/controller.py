@@ -181,10 +181,11 @@ class Controller:
         native.check(native.lib().mppi_jump_profile(self.ctx, int(bool(enable))))
 
     def profile_read(self):
-        """(summed rollout-kernel ms, launches) since the last read."""
-        ms, n = ctypes.c_double(), ctypes.c_int64()
-        native.check(native.lib().mppi_jump_profile_read(self.ctx, ctypes.byref(ms), ctypes.byref(n)))
-        return ms.value, n.value
+        """(summed rollout-kernel ms, launches, iterations) since the last read."""
+        ms, n, it = ctypes.c_double(), ctypes.c_int64(), ctypes.c_int64()
+        native.check(native.lib().mppi_jump_profile_read(self.ctx, ctypes.byref(ms), ctypes.byref(n),
+                                                         ctypes.byref(it)))
+        return ms.value, n.value, it.value
 
 
 class Batch:

@@ -30,6 +30,8 @@ struct alignas(128) WgPartial {
   int32_t nfin;  // number of finite S_k
 };
 
+constexpr int kCounters = 2;
+
 struct DevParams {
   int K, T, Ks, n_th;
   uint32_t k0;                // global index of sample 0 (Philox counter)
@@ -63,7 +65,7 @@ struct Buffers {
   double* upart;      // [T*m][nch]   chunk partials of update_kernel
   double* wpart;      // [nwg][T*m]   workgroup partials of the fused epilogue
   mppi_jump_stats* stats;
-  uint32_t* counters; // [0] rollout, [1] update
+  uint32_t* counters; // [kCounters]: [0] rollout arrivals, [1] update arrivals
   float* dbg_zD;      // [K][T][m]
   int32_t* dbg_N;     // [K][T]
   float* dbg_zJ;      // [K][T][q]
@@ -124,37 +126,35 @@ constexpr int kStageRows = 1024;  // partial rows staged in LDS per pass
 __device__ __forceinline__ void release_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 __device__ __forceinline__ void acquire_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
-// Rollout epilogue over the SPW samples of this workgroup (threads below SPW
-// hold a cost; the others pass active = false):
-//   * statistics of eq. (37): rho_wg = min of the finite S_k, E_k =
-//     exp(-(S_k - rho_wg)/lambda), eta_wg = sum E_k, count of finite S_k;
-//   * FUSED: the weighted perturbation sums P[r][wg] = sum_k E_k eps[r][k]
-//     over the workgroup's own eps tile;
-//   * the last workgroup to arrive combines the partials in index order with
-//     the rescale exp(-(rho_wg - rho)/lambda) and, when FUSED, applies
-//     U[r] += alpha * sum_wg scale_wg P[r][wg] / eta (eqs. (36) / (49)) and
-//     advances the iteration counter.
-// Publication: every global partial is stored by wavefront 0, which then
-// issues the workgroup's single device-scope release fence before the
-// arrival counter is incremented (a device-scope release writes back the L2
-// of this XCD, so one per workgroup instead of one per wavefront).
-// wg / nwg: this workgroup's index among the nwg workgroups of its controller.
+// Rollout epilogue, in three parts that the one-iteration kernels chain with
+// a last-arrival hand-off and the multi-iteration kernel with a grid-wide
+// wait:
+//   * publish: statistics of eq. (37) over the SPW samples of this
+//     workgroup (threads below SPW hold a cost; the others pass active =
+//     false): rho_wg = min of the finite S_k, E_k = exp(-(S_k - rho_wg)/
+//     lambda), eta_wg = sum E_k, count of finite S_k; FUSED: the weighted
+//     perturbation sums P[r][wg] = sum_k E_k eps[r][k] over the workgroup's
+//     own eps tile.  Every global partial is stored by wavefront 0, so that
+//     the single device-scope release fence that wavefront issues next
+//     covers them all (a device-scope release writes back the L2 of this
+//     XCD, so one per workgroup instead of one per wavefront).
+//   * combine: the partials in index order with the rescale
+//     exp(-(rho_wg - rho)/lambda), and, when FUSED,
+//     U[r] += alpha * sum_wg scale_wg P[r][wg] / eta (eqs. (36) / (49)).
+//   * the receding-horizon shift and the statistics record.
 // tile / tstride (FUSED): the workgroup's perturbations, row r (= t m + j)
 // of its SPW samples at tile[r tstride ..] (on chip, or its columns of the
-// HBM array).
-template <int SPW, bool FUSED, int NT = kBlock>
-__device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffers& b, double Sd,
-                                                 bool active, int R, const ShiftArgs sh, int wg,
-                                                 int nwg, const float* tile, int tstride) {
+// HBM array).  part / wpart: where this workgroup's partials go (row r of
+// workgroup wg at wpart[wg R + r]).
+template <int SPW, bool FUSED, int NT>
+__device__ __forceinline__ void epilogue_publish(const DevParams& p, const Buffers& b, double Sd,
+                                                 bool active, int R, int wg, const float* tile,
+                                                 int tstride, WgPartial* part, double* wpart) {
   constexpr int NW = NT / 64;
   constexpr int RPP = NT / 4;  // eps tile rows per pass, four threads per row
   __shared__ double lds[NW];
   __shared__ double e_lds[SPW];
   __shared__ double stage[FUSED ? kStageRows : 1];
-  __shared__ double sc_lds[FUSED ? kFusedMaxWg : 1];
-  __shared__ double seg_lds[FUSED ? NT : 1];
-  __shared__ double bc[3];
-  __shared__ int is_last;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const bool fin = active && isfinite(Sd);
   const int k0 = wg * SPW;
@@ -211,28 +211,38 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
       }
       __syncthreads();
       if (wave == 0)
-        for (int i = lane; i < nrow; i += 64) b.wpart[(size_t)wg * R + base + i] = stage[i];
+        for (int i = lane; i < nrow; i += 64) wpart[(size_t)wg * R + base + i] = stage[i];
       __syncthreads();
     }
   }
-  if (wave == 0) {
-    if (lane == 0) {
-      b.part[wg].rho = rho_wg;
-      b.part[wg].eta = eta_wg;
-      b.part[wg].nfin = (int32_t)nfin;
-    }
-    release_fence();
-    if (lane == 0) {
-      const uint32_t prev = atomicAdd(&b.counters[0], 1u);
-      is_last = (prev == (uint32_t)nwg - 1);
-    }
+  if (wave == 0 && lane == 0) {
+    part[wg].rho = rho_wg;
+    part[wg].eta = eta_wg;
+    part[wg].nfin = (int32_t)nfin;
   }
-  __syncthreads();
-  if (!is_last) return;
-  acquire_fence();
-  const WgPartial* parts = b.part;
-  const double* rows = b.wpart;  // row r of partial j at rows[j R + r]
-  const int n = nwg;
+}
+
+// Combination of n partials (every thread of the workgroup takes part; the
+// partials are visible to it).  Returns (rho, eta, count of finite S_k) to
+// every thread.  FUSED: Uout[r] = Uin[r] + alpha / eta * sum_j scale_j
+// P[r][j] for every row (unchanged when no S_k is finite); Uin and Uout may
+// be the same array (global or LDS).  scale (may be null): the rescales
+// exp(-(rho_j - rho)/lambda) are stored there too.
+struct Combined {
+  double rho, eta, cnt;
+};
+
+template <bool FUSED, int NT>
+__device__ __forceinline__ Combined epilogue_combine(const DevParams& p, const WgPartial* parts,
+                                                     const double* rows, int n, int R,
+                                                     const float* Uin, float* Uout,
+                                                     double* scale) {
+  constexpr int NW = NT / 64;
+  __shared__ double lds[NW];
+  __shared__ double sc_lds[FUSED ? kFusedMaxWg : 1];
+  __shared__ double seg_lds[FUSED ? NT : 1];
+  __shared__ double bc[3];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
   // First pass of the fused update (rows [0, Rp)): when there are threads
   // to spare, each row's partials are split into S contiguous segments, one
@@ -253,7 +263,7 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
     const double* wr = rows + rr;
 #pragma unroll
     for (int q = 0; q < kPre; ++q) wpre[q] = j0 + q < j1 ? wr[(size_t)(j0 + q) * R] : 0.0;
-    if (seg == 0) uold = b.U[rr];
+    if (seg == 0) uold = Uin[rr];
   }
   // combination: rho = min of the partial minima, the rescales
   // exp(-(rho_j - rho)/lambda), eta and the finite count.  Up to 64
@@ -269,7 +279,7 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
       double eta = 0.0, cnt = 0.0;
       if (h) {
         const double sc = hfin > 0 ? exp(-(hrho - rho) / p.lam_d) : 0.0;
-        b.scale[lane] = sc;
+        if (scale != nullptr) scale[lane] = sc;
         if constexpr (FUSED) sc_lds[lane] = sc;
         eta = heta * sc;
         cnt = hfin;
@@ -298,7 +308,7 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
     for (int j = threadIdx.x; j < n; j += NT) {
       const WgPartial q = j < NT ? q0 : parts[j];
       const double sc = (q.nfin > 0) ? exp(-(q.rho - rho) / p.lam_d) : 0.0;
-      b.scale[j] = sc;
+      if (scale != nullptr) scale[j] = sc;
       if constexpr (FUSED) sc_lds[j] = sc;
       eta += q.eta * sc;
       cnt += q.nfin;
@@ -312,14 +322,13 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
     }
   }
   __syncthreads();  // bc and sc_lds
-  const double rho = bc[0], eta = bc[1], cnt = bc[2];
-  const bool ok = cnt > 0;
+  const Combined out{bc[0], bc[1], bc[2]};
   if constexpr (FUSED) {
     // U[r] += alpha / eta * sum_j scale_j P[r][j]: each segment is summed
     // with four accumulators in a fixed pattern, the segment sums in segment
     // order
-    if (ok) {
-      const double f = (double)p.alpha / eta;
+    if (out.cnt > 0) {
+      const double f = (double)p.alpha / out.eta;
       for (int base = 0; base < R; base += NT) {
         const bool first = base == 0;
         if (!first) {
@@ -392,39 +401,81 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
             for (int s2 = 1; s2 < S; ++s2) acc += seg_lds[s2 * Rp + rr];
         }
         if (seg == 0) {
-          const float uo = first ? uold : b.U[base + rr];
-          b.U[base + rr] = (float)((double)uo + f * acc);
+          const float uo = first ? uold : Uin[base + rr];
+          Uout[base + rr] = (float)((double)uo + f * acc);
         }
         if (S > 1) __syncthreads();
       }
     }
+  }
+  return out;
+}
+
+// Receding-horizon shift of U (R floats, m per step) by the whole
+// workgroup, after its update is visible to the workgroup: u0_out[0..m) <-
+// U[0] (may be null), U[t] <- U[t+1], U[T-1] <- u_init.  Uin and Uout may be
+// the same array.
+template <int NT>
+__device__ __forceinline__ void epilogue_shift(const ShiftArgs& sh, const float* Uin, float* Uout,
+                                               int R) {
+  const int m = sh.m;
+  if (sh.u0_out != nullptr && threadIdx.x < m) sh.u0_out[threadIdx.x] = Uin[threadIdx.x];
+  for (int base = 0; base < R; base += NT) {
+    const int r = base + threadIdx.x;
+    float v = 0.f;
+    if (r < R) {
+      if (r + m < R) {
+        v = Uin[r + m];
+      } else {
+        const int j = r - (R - m);
+        v = j == 0 ? sh.u_init.x : j == 1 ? sh.u_init.y : j == 2 ? sh.u_init.z : sh.u_init.w;
+      }
+    }
+    __syncthreads();
+    if (r < R) Uout[r] = v;
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void record_stats(const Buffers& b, const Combined& c,
+                                             uint64_t iteration, bool advance) {
+  b.stats->rho = c.rho;
+  b.stats->eta = c.eta;
+  b.stats->n_finite = (int32_t)c.cnt;
+  b.stats->status = c.cnt > 0 ? MPPI_OK : MPPI_ENONFINITE;
+  if (advance) b.stats->iteration = iteration;
+}
+
+// The one-iteration epilogue: publish, then the last workgroup to arrive
+// combines, applies the update (FUSED) and, when sh.on, the shift, records
+// the statistics and advances the iteration counter (FUSED).
+// wg / nwg: this workgroup's index among the nwg workgroups of its controller.
+template <int SPW, bool FUSED, int NT = kBlock>
+__device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffers& b, double Sd,
+                                                 bool active, int R, const ShiftArgs sh, int wg,
+                                                 int nwg, const float* tile, int tstride) {
+  __shared__ int is_last;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  epilogue_publish<SPW, FUSED, NT>(p, b, Sd, active, R, wg, tile, tstride, b.part, b.wpart);
+  if (wave == 0) {
+    release_fence();
+    if (lane == 0) {
+      const uint32_t prev = atomicAdd(&b.counters[0], 1u);
+      is_last = (prev == (uint32_t)nwg - 1);
+    }
+  }
+  __syncthreads();
+  if (!is_last) return;
+  acquire_fence();
+  const Combined c = epilogue_combine<FUSED, NT>(p, b.part, b.wpart, nwg, R, b.U, b.U, b.scale);
+  if constexpr (FUSED) {
     if (sh.on) {
       __syncthreads();  // the updated rows are visible to the whole block
-      const int m = sh.m;
-      if (sh.u0_out != nullptr && threadIdx.x < m) sh.u0_out[threadIdx.x] = b.U[threadIdx.x];
-      for (int base = 0; base < R; base += NT) {
-        const int r = base + threadIdx.x;
-        float v = 0.f;
-        if (r < R) {
-          if (r + m < R) {
-            v = b.U[r + m];
-          } else {
-            const int j = r - (R - m);
-            v = j == 0 ? sh.u_init.x : j == 1 ? sh.u_init.y : j == 2 ? sh.u_init.z : sh.u_init.w;
-          }
-        }
-        __syncthreads();
-        if (r < R) b.U[r] = v;
-        __syncthreads();
-      }
+      epilogue_shift<NT>(sh, b.U, b.U, R);
     }
   }
   if (threadIdx.x == 0) {
-    b.stats->rho = rho;
-    b.stats->eta = eta;
-    b.stats->n_finite = (int32_t)cnt;
-    b.stats->status = ok ? MPPI_OK : MPPI_ENONFINITE;
-    if constexpr (FUSED) b.stats->iteration = b.stats->iteration + 1;
+    record_stats(b, c, b.stats->iteration + 1, FUSED);
     b.counters[0] = 0u;
   }
 }
@@ -743,8 +794,7 @@ __global__ void init_kernel(Buffers b, const float* __restrict__ U0, int R, int 
     b.stats->status = MPPI_OK;
     b.stats->n_finite = 0;
     b.stats->iteration = start_iteration;
-    b.counters[0] = 0u;
-    b.counters[1] = 0u;
+    for (int i = 0; i < kCounters; ++i) b.counters[i] = 0u;
   }
 }
 
@@ -758,8 +808,7 @@ __global__ void stats_init_kernel(Buffers b, uint64_t start_iteration) {
     b.stats->status = MPPI_OK;
     b.stats->n_finite = 0;
     b.stats->iteration = start_iteration;
-    b.counters[0] = 0u;
-    b.counters[1] = 0u;
+    for (int i = 0; i < kCounters; ++i) b.counters[i] = 0u;
   }
 }
 

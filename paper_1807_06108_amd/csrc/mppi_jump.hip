@@ -220,7 +220,7 @@ Layout make_layout(const mppi_jump_config* c, int m, int q) {
   L.eps_lds = L.ws && L.fused && !c->debug_dump && fits;
   L.wpart = take(L.fused ? (size_t)L.nwg * L.R * 8 : 0);
   L.stats = take(sizeof(mppi_jump_stats));
-  L.counters = take(2 * sizeof(uint32_t));
+  L.counters = take(kCounters * sizeof(uint32_t));
   L.W = take(K * 8);
   if (c->debug_dump) {
     L.zD = take(K * T * m * 4);
@@ -333,7 +333,7 @@ struct mppi_jump_ctx {
   bool profiling = false;
   struct Bracket {
     hipEvent_t e0, e1;
-    int launches;
+    int launches, iterations;
   };
   std::vector<Bracket> events;  // one pair per bracketed span of rollout launches
   size_t events_used = 0;
@@ -370,21 +370,32 @@ void bind_context(mppi_jump_ctx* ctx, const mppi_jump_config* cfg, int n, int m,
   ctx->host_iteration = cfg->start_iteration;
 }
 
-// The fused wave-specialised kernel with its perturbation tile on chip: its
-// dynamic LDS (ring plus tile) can exceed the default launch limit, so the
-// kernel's limit is raised once, to the compute unit's LDS less the static
-// part bounded by kWsStaticLds.
-template <int DYN, bool JUMPS, int FORM, bool FULL>
-int launch_ws_eps_lds(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, const ShiftArgs& sh) {
-  const auto kern = rollout_ws_kernel<DYN, JUMPS, false, FORM, true, FULL, true>;
-  static const hipError_t raised = hipFuncSetAttribute(
-      reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
-      (int)(kLdsBytes - kWsStaticLds));
-  if (raised != hipSuccess)
+// A wave-specialised kernel's dynamic LDS (ring, the perturbation tile when
+// on chip, U) can exceed the default launch limit, so each kernel's limit is
+// raised once, to the compute unit's LDS less the static part bounded by
+// kWsStaticLds; that bound is checked then too.
+int raise_ws_lds_limit(const void* kern) {
+  const hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)(kLdsBytes - kWsStaticLds));
+  if (e != hipSuccess)
     return fail(MPPI_EDEVICE, "raising the LDS limit of rollout_ws_kernel: %s",
-                hipGetErrorString(raised));
-  kern<<<dim3(ctx->L.nwg), dim3(64 * WsWaves<DYN>::W), ws_eps_lds_bytes<DYN>(ctx->L.R), s>>>(
-      ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R, sh);
+                hipGetErrorString(e));
+  hipFuncAttributes a{};
+  HIP_TRY(hipFuncGetAttributes(&a, kern));
+  if (a.sharedSizeBytes > kWsStaticLds)
+    return fail(MPPI_EDEVICE, "rollout_ws_kernel holds %zu bytes of static LDS, above %zu",
+                a.sharedSizeBytes, kWsStaticLds);
+  return MPPI_OK;
+}
+
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL, bool EPS_LDS>
+int launch_ws(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, const ShiftArgs& sh) {
+  const auto kern = rollout_ws_kernel<DYN, JUMPS, DEBUG, FORM, FUSED, FULL, EPS_LDS>;
+  static const int raised = raise_ws_lds_limit(reinterpret_cast<const void*>(kern));
+  if (raised != MPPI_OK) return fail(raised, "%s", "the LDS limit of rollout_ws_kernel");
+  const size_t lds = EPS_LDS ? ws_eps_lds_bytes<DYN>(ctx->L.R) : ws_lds_bytes<DYN>(ctx->L.R);
+  kern<<<dim3(ctx->L.nwg), dim3(64 * WsWaves<DYN>::W), lds, s>>>(ctx->p, ctx->b, x0, ctx->b.U,
+                                                                 ctx->L.R, sh);
   LAUNCH_CHECK("rollout_ws_kernel");
   return MPPI_OK;
 }
@@ -393,13 +404,10 @@ template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL>
 int launch_rollout_t(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, const ShiftArgs& sh) {
   ctx->eps_stored = !(FUSED && !DEBUG && ctx->L.eps_lds);
   if constexpr (FUSED && !DEBUG) {
-    if (ctx->L.eps_lds) return launch_ws_eps_lds<DYN, JUMPS, FORM, FULL>(ctx, x0, s, sh);
+    if (ctx->L.eps_lds) return launch_ws<DYN, JUMPS, DEBUG, FORM, FUSED, FULL, true>(ctx, x0, s, sh);
   }
   if (ctx->L.ws) {
-    rollout_ws_kernel<DYN, JUMPS, DEBUG, FORM, FUSED, FULL, false>
-        <<<dim3(ctx->L.nwg), dim3(64 * WsWaves<DYN>::W), ws_ring_bytes<DYN>(), s>>>(
-            ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R, sh);
-    LAUNCH_CHECK("rollout_ws_kernel");
+    return launch_ws<DYN, JUMPS, DEBUG, FORM, FUSED, FULL, false>(ctx, x0, s, sh);
   } else {
     rollout_kernel<DYN, JUMPS, DEBUG, FORM, FUSED, FULL>
         <<<dim3(ctx->L.nwg), dim3(kBlock), 0, s>>>(ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R, sh);
@@ -456,10 +464,11 @@ int bracket_begin(mppi_jump_ctx* ctx, hipStream_t s) {
   return MPPI_OK;
 }
 
-int bracket_end(mppi_jump_ctx* ctx, hipStream_t s, int launches) {
+int bracket_end(mppi_jump_ctx* ctx, hipStream_t s, int launches, int iterations) {
   if (!ctx->profiling) return MPPI_OK;
   HIP_TRY(hipEventRecord(ctx->events[ctx->events_used].e1, s));
   ctx->events[ctx->events_used].launches = launches;
+  ctx->events[ctx->events_used].iterations = iterations;
   ctx->events_used++;
   return MPPI_OK;
 }
@@ -478,7 +487,7 @@ int launch_rollout(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, bool fuse
     default: rc = launch_rollout_dyn<MPPI_DYN_QUADROTOR>(ctx, x0, s, fused, sh); break;
   }
   if (rc != MPPI_OK) return rc;
-  return own_bracket ? bracket_end(ctx, s, 1) : MPPI_OK;
+  return own_bracket ? bracket_end(ctx, s, 1, 1) : MPPI_OK;
 }
 
 int launch_update(mppi_jump_ctx* ctx, hipStream_t s) {
@@ -614,7 +623,7 @@ int mppi_jump_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, void* s
       ctx->host_iteration += 1;
     }
     if (span) {
-      const int rb = bracket_end(ctx, s, iters);
+      const int rb = bracket_end(ctx, s, iters, iters);
       if (rb != MPPI_OK) return rb;
     }
     return ok();
@@ -648,7 +657,7 @@ int enqueue_control_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, f
     if (rc != MPPI_OK) return rc;
     ctx->host_iteration += 1;
   }
-  rc = bracket_end(ctx, s, iters);
+  rc = bracket_end(ctx, s, iters, iters);
   return rc == MPPI_OK ? ok() : rc;
 }
 
@@ -1462,20 +1471,23 @@ int mppi_jump_profile(mppi_jump_ctx* ctx, int32_t enable) {
   return ok();
 }
 
-int mppi_jump_profile_read(mppi_jump_ctx* ctx, double* total_ms, int64_t* launches) {
+int mppi_jump_profile_read(mppi_jump_ctx* ctx, double* total_ms, int64_t* launches,
+                           int64_t* iterations) {
   return guarded([&]() -> int {
-    if (!ctx || !total_ms || !launches) return fail(MPPI_EINVAL, "NULL argument");
+    if (!ctx || !total_ms || !launches || !iterations) return fail(MPPI_EINVAL, "NULL argument");
     double tot = 0.0;
-    int64_t n = 0;
+    int64_t n = 0, ni = 0;
     for (size_t i = 0; i < ctx->events_used; ++i) {
       HIP_TRY(hipEventSynchronize(ctx->events[i].e1));
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, ctx->events[i].e0, ctx->events[i].e1));
       tot += ms;
       n += ctx->events[i].launches;
+      ni += ctx->events[i].iterations;
     }
     *total_ms = tot;
     *launches = n;
+    *iterations = ni;
     ctx->events_used = 0;
     return ok();
   });

@@ -97,11 +97,20 @@ constexpr size_t ws_ring_bytes() {
 // ring and the tile fit beside the kernel's static LDS: T <= 496 for the
 // one-channel models, T <= 108 for the 12-state model (whose ring then omits
 // v, above).
+// The single-controller kernels also stage the control sequence U (R
+// floats) after the ring and the tile: read once at kernel start, all lines
+// at once, instead of one L2 miss after another as the producers reach new
+// steps (the sequence was just written by the previous launch, on another
+// XCD).
 constexpr size_t kLdsBytes = 160 * 1024;     // LDS of a gfx950 compute unit
-constexpr size_t kWsStaticLds = 20 * 1024;   // bound on the kernel's static LDS
+constexpr size_t kWsStaticLds = 18 * 1024;   // bound on the kernel's static LDS
+template <int DYN>
+constexpr size_t ws_lds_bytes(int R) {
+  return ws_ring_bytes<DYN, false>() + sizeof(float) * (size_t)R;
+}
 template <int DYN>
 constexpr size_t ws_eps_lds_bytes(int R) {
-  return ws_ring_bytes<DYN, true>() + sizeof(float) * (size_t)R * kWsSamples;
+  return ws_ring_bytes<DYN, true>() + sizeof(float) * (size_t)R * (kWsSamples + 1);
 }
 template <int DYN>
 constexpr bool ws_eps_fits(int R) {
@@ -242,17 +251,17 @@ __device__ __forceinline__ void ws_consume_chunk(const DevParams& p, const Const
   }
 }
 
-// One workgroup (tile wg of nwg) of the wave-specialised rollout, W waves.
-template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, int W, bool FULL = false,
-          bool EPS_LDS = false>
-__device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffers& b,
-                                                const float* __restrict__ x0,
-                                                const float* U, int R,
-                                                const ShiftArgs& sh, int wg, int nwg) {
+// The rollout of one workgroup (tile wg, W waves) at iteration `it`:
+// returns S~_k of sample wg * 64 + lane in wavefront 0 (also stored to b.S).
+// cs: the staged constants; U: the control sequence (global memory or LDS).
+// With EPS_LDS the perturbation tile is left on chip for the epilogue.
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, int W, bool FULL, bool EPS_LDS>
+__device__ __forceinline__ double ws_rollout(const DevParams& p, const Consts& cs,
+                                             const Buffers& b, const float* __restrict__ x0,
+                                             const float* U, int wg, uint32_t it) {
   using Md = Model<DYN>;
   using Rg = WsRing<DYN, EPS_LDS>;
   constexpr int N = Md::N;
-  static_assert(!EPS_LDS || FUSED, "the on-chip tile serves the fused epilogue");
   constexpr int NP = W - 1;  // producer waves
   constexpr int CH = kWsChunk;
   constexpr int SLOT = Rg::NF * 64;  // floats per (step) slot
@@ -265,11 +274,8 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int k = wg * kWsSamples + lane;
   const bool active = k < p.K;
-  const uint32_t it = (uint32_t)b.stats->iteration;
   const int T = p.T;
   const int nch = (T + CH - 1) / CH;
-  __shared__ Consts cs;
-  stage_consts(cs, p);
 
   // eight waves: this producer's contiguous range of each chunk's steps
   int s0 = 0, s1 = 0;
@@ -336,12 +342,37 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
     Sd = st.S.S + (double)qf;
     if (active) b.S[k] = Sd;
   }
+  return Sd;
+}
+
+// One workgroup (tile wg of nwg) of the wave-specialised rollout, W waves,
+// with its one-iteration epilogue.  U_LDS: U is staged in LDS after the
+// ring and the tile (the single-controller kernels; the batched ones, whose
+// controllers differ in R, read it from global memory).
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, int W, bool FULL = false,
+          bool EPS_LDS = false, bool U_LDS = false>
+__device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffers& b,
+                                                const float* __restrict__ x0,
+                                                const float* U, int R,
+                                                const ShiftArgs& sh, int wg, int nwg) {
+  static_assert(!EPS_LDS || FUSED, "the on-chip tile serves the fused epilogue");
+  extern __shared__ float ws_dyn_lds[];
+  constexpr int kRingFloats = 2 * kWsChunk * WsRing<DYN, EPS_LDS>::NF * 64;
+  float* Ul = ws_dyn_lds + kRingFloats + (EPS_LDS ? (size_t)R * kWsSamples : 0);
+  if constexpr (U_LDS)
+    for (int r = threadIdx.x; r < R; r += 64 * W) Ul[r] = U[r];
+  __shared__ Consts cs;
+  stage_consts(cs, p);  // its barrier also publishes Ul
+  const uint32_t it = (uint32_t)b.stats->iteration;
+  const double Sd = ws_rollout<DYN, JUMPS, DEBUG, FORM, W, FULL, EPS_LDS>(
+      p, cs, b, x0, U_LDS ? static_cast<const float*>(Ul) : U, wg, it);
   // the epilogue's weighted sums read the tile on chip, or the workgroup's
   // columns of the HBM perturbations
-  const float* tile = EPS_LDS ? epsl : b.eps + (size_t)wg * kWsSamples;
+  const float* tile = EPS_LDS ? ws_dyn_lds + kRingFloats : b.eps + (size_t)wg * kWsSamples;
   const int tstride = EPS_LDS ? kWsSamples : p.Ks;
-  rollout_epilogue<kWsSamples, FUSED, 64 * W>(p, b, Sd, wave == 0 && active, R, sh, wg, nwg,
-                                              tile, tstride);
+  const int k = wg * kWsSamples + (threadIdx.x & 63);
+  rollout_epilogue<kWsSamples, FUSED, 64 * W>(p, b, Sd, (threadIdx.x >> 6) == 0 && k < p.K, R,
+                                              sh, wg, nwg, tile, tstride);
 }
 
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL, bool EPS_LDS>
@@ -350,7 +381,7 @@ __global__ __launch_bounds__(64 * WsWaves<DYN>::W) void rollout_ws_kernel(const 
                                                                          const float* __restrict__ x0,
                                                                          const float* U,
                                                                          int R, const ShiftArgs sh) {
-  rollout_ws_tile<DYN, JUMPS, DEBUG, FORM, FUSED, WsWaves<DYN>::W, FULL, EPS_LDS>(
+  rollout_ws_tile<DYN, JUMPS, DEBUG, FORM, FUSED, WsWaves<DYN>::W, FULL, EPS_LDS, true>(
       p, b, x0, U, R, sh, blockIdx.x, gridDim.x);
 }
 

@@ -152,6 +152,7 @@ _PROTOS = {
                                         ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]),
     "mppi_jump_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "mppi_jump_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                              ctypes.POINTER(ctypes.c_int64),
                                               ctypes.POINTER(ctypes.c_int64)]),
 }
 

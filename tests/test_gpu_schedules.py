@@ -118,3 +118,4 @@ def test_control_step_equals_step_then_shift(preset, K, T, iters):
     u1_a = a.shift().cpu().numpy()
     u1_b = b.control_step(x0, 1).cpu().numpy()
     assert np.array_equal(u1_a, u1_b)
+
