@@ -1,4 +1,5 @@
-"""Build of the HIP library libmppi_jump.so for gfx950 (in-tree)."""
+"""Build of the HIP library libmppi_jump.so for gfx950 (in-tree), of its
+phase-profiling variant and of the issue-rate probe."""
 
 import os
 import shutil
@@ -44,6 +45,12 @@ def hipcc():
     raise RuntimeError("hipcc not found")
 
 
+# The phase-profiling build: the same sources with per-workgroup phase
+# timestamps compiled in (MPPI_PHASE_STAMPS; include/mppi_jump_phases.h),
+# loaded only by phase_profile.py.
+PHASE_LIB = os.path.join(HERE, "libmppi_jump_phases.so")
+
+
 def build(extra_flags=(), out=LIB, verbose=False):
     """Compile the library; returns its path.  Always recompiles."""
     tmp = out + ".tmp"
@@ -52,6 +59,11 @@ def build(extra_flags=(), out=LIB, verbose=False):
     run(cmd, verbose)
     os.replace(tmp, out)
     return out
+
+
+def build_phases(verbose=False):
+    """Compile the phase-profiling library; returns its path."""
+    return build(extra_flags=["-DMPPI_PHASE_STAMPS"], out=PHASE_LIB, verbose=verbose)
 
 
 # Measurement probe (an executable for gfx950): the VALU issue rates of the
@@ -72,4 +84,5 @@ def build_probe(verbose=False):
 
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_phases(verbose=True))
     print(build_probe(verbose=True))

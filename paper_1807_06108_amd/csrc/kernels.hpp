@@ -126,6 +126,31 @@ constexpr int kStageRows = 1024;  // partial rows staged in LDS per pass
 __device__ __forceinline__ void release_fence() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
 __device__ __forceinline__ void acquire_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
+// Phase timestamps, compiled only into the phase-profiling build of the
+// library (MPPI_PHASE_STAMPS defined): thread 0 of every workgroup of the
+// wave-specialised rollout records the 100 MHz real-time counter at the
+// phase boundaries of one iteration, in the record of launch (iteration
+// mod kPhaseLaunches).  Slots: 0 workgroup start, 1 rollout done (costs
+// known), 2 partials stored, 3 arrival counted, 4 combine done and 5
+// epilogue done (the last workgroup only), 6 one for the last workgroup,
+// else zero, 7 the consumer's first chunk ready, 8 acquire done and 9
+// statistics combined (the last workgroup).
+#ifdef MPPI_PHASE_STAMPS
+constexpr int kPhaseSlots = 16, kPhaseLaunches = 8, kPhaseMaxWg = 256;
+__device__ unsigned long long g_phase[kPhaseLaunches * kPhaseMaxWg * kPhaseSlots];
+__device__ __forceinline__ void phase_mark(uint64_t it, int wg, int nwg, int slot,
+                                           unsigned long long v) {
+  if (threadIdx.x == 0 && wg < kPhaseMaxWg && nwg <= kPhaseMaxWg)
+    g_phase[((it % kPhaseLaunches) * kPhaseMaxWg + wg) * kPhaseSlots + slot] = v;
+}
+#define MPPI_PHASE(it, wg, nwg, slot) \
+  phase_mark((it), (wg), (nwg), (slot), __builtin_amdgcn_s_memrealtime())
+#define MPPI_PHASE_VALUE(it, wg, nwg, slot, v) phase_mark((it), (wg), (nwg), (slot), (v))
+#else
+#define MPPI_PHASE(it, wg, nwg, slot) ((void)0)
+#define MPPI_PHASE_VALUE(it, wg, nwg, slot, v) ((void)0)
+#endif
+
 // Rollout epilogue, in three parts that the one-iteration kernels chain with
 // a last-arrival hand-off and the multi-iteration kernel with a grid-wide
 // wait:
@@ -456,7 +481,12 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
                                                  int nwg, const float* tile, int tstride) {
   __shared__ int is_last;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#ifdef MPPI_PHASE_STAMPS
+  const uint64_t it = b.stats->iteration;
+#endif
+  MPPI_PHASE(it, wg, nwg, 1);
   epilogue_publish<SPW, FUSED, NT>(p, b, Sd, active, R, wg, tile, tstride, b.part, b.wpart);
+  MPPI_PHASE(it, wg, nwg, 2);
   if (wave == 0) {
     release_fence();
     if (lane == 0) {
@@ -465,15 +495,20 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
     }
   }
   __syncthreads();
+  MPPI_PHASE(it, wg, nwg, 3);
+  MPPI_PHASE_VALUE(it, wg, nwg, 6, is_last ? 1ull : 0ull);
   if (!is_last) return;
   acquire_fence();
+  MPPI_PHASE(it, wg, nwg, 8);
   const Combined c = epilogue_combine<FUSED, NT>(p, b.part, b.wpart, nwg, R, b.U, b.U, b.scale);
+  MPPI_PHASE(it, wg, nwg, 4);
   if constexpr (FUSED) {
     if (sh.on) {
       __syncthreads();  // the updated rows are visible to the whole block
       epilogue_shift<NT>(sh, b.U, b.U, R);
     }
   }
+  MPPI_PHASE(it, wg, nwg, 5);
   if (threadIdx.x == 0) {
     record_stats(b, c, b.stats->iteration + 1, FUSED);
     b.counters[0] = 0u;

@@ -319,6 +319,7 @@ __device__ __forceinline__ double ws_rollout(const DevParams& p, const Consts& c
   } else {
     constexpr int kUnroll = WsConsumeUnroll<DYN>::U;
     __syncthreads();
+    MPPI_PHASE(b.stats->iteration, wg, (p.K + kWsSamples - 1) / kWsSamples, 7);
     for (int cc = 0; cc < nch; ++cc) {
       float(*buf)[SLOT] = ring[cc & 1];
       if ((cc + 1) * CH <= T)
@@ -356,6 +357,7 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
                                                 const float* U, int R,
                                                 const ShiftArgs& sh, int wg, int nwg) {
   static_assert(!EPS_LDS || FUSED, "the on-chip tile serves the fused epilogue");
+  MPPI_PHASE(b.stats->iteration, wg, nwg, 0);
   extern __shared__ float ws_dyn_lds[];
   constexpr int kRingFloats = 2 * kWsChunk * WsRing<DYN, EPS_LDS>::NF * 64;
   float* Ul = ws_dyn_lds + kRingFloats + (EPS_LDS ? (size_t)R * kWsSamples : 0);

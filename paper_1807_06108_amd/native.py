@@ -157,6 +157,15 @@ _PROTOS = {
 }
 
 
+def use_library(path):
+    """Load the library from `path` instead (the phase-profiling build);
+    only before the first load."""
+    global LIB_PATH
+    if _lib is not None and path != LIB_PATH:
+        raise RuntimeError("the library is already loaded from %s" % LIB_PATH)
+    LIB_PATH = path
+
+
 def lib():
     """The loaded library (raises if it has not been built)."""
     global _lib
