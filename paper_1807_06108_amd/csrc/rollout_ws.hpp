@@ -291,12 +291,25 @@ __device__ __forceinline__ double ws_rollout(const DevParams& p, const Consts& c
   st.crashed = Md::CAN_CRASH ? Md::crashed(st.x, cs.mc) : false;
   st.S = CostSum{};
 
-  // Producers and the consumer run separate loops (the branch is uniform per
-  // wavefront), so the register allocation of each holds only its own live
-  // values and constants, not the union of both.  Both loops pass nch + 1
-  // barriers: chunk c is produced before barrier c and consumed after it.
+  // The first chunk is produced by all W waves (the consumer has nothing
+  // to do before it), CH / W steps each, so the recursion starts sooner.
+  // Then producers and the consumer run separate loops (the branch is
+  // uniform per wavefront), so the register allocation of each holds only
+  // its own live values and constants, not the union of both.  Both sides
+  // pass nch + 1 barriers: chunk c is produced before barrier c and consumed
+  // after it.
+  static_assert(CH % W == 0, "the first chunk splits evenly over the waves");
+  {
+    const int w = __builtin_amdgcn_readfirstlane(wave);
+    for (int s = w * (CH / W); s < (w + 1) * (CH / W); ++s)
+      if (s < T)
+        ws_produce<DYN, JUMPS, DEBUG, FORM, FULL, EPS_LDS>(p, cs, b, U, ring[0][s], epsl, s, k,
+                                                            active, it);
+  }
+  __syncthreads();
+  MPPI_PHASE(b.stats->iteration, wg, (p.K + kWsSamples - 1) / kWsSamples, 7);
   if (__builtin_amdgcn_readfirstlane(wave) > 0) {
-    for (int c = 0; c < nch; ++c) {
+    for (int c = 1; c < nch; ++c) {
       float(*buf)[SLOT] = ring[c & 1];
       if constexpr (W == 8) {
         for (int s = s0; s < s1; ++s) {
@@ -318,8 +331,6 @@ __device__ __forceinline__ double ws_rollout(const DevParams& p, const Consts& c
     __syncthreads();
   } else {
     constexpr int kUnroll = WsConsumeUnroll<DYN>::U;
-    __syncthreads();
-    MPPI_PHASE(b.stats->iteration, wg, (p.K + kWsSamples - 1) / kWsSamples, 7);
     for (int cc = 0; cc < nch; ++cc) {
       float(*buf)[SLOT] = ring[cc & 1];
       if ((cc + 1) * CH <= T)
