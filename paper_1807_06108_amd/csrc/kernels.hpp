@@ -766,7 +766,14 @@ __global__ __launch_bounds__(256) void restats_kernel(const DevParams p, const B
 }
 
 // ------------------------------------------------------------------ update
-constexpr int kRowsPerWg = 8;
+// A workgroup takes kRowsPerWg rows of eps over one chunk of samples; each
+// thread four consecutive samples at a time (one 16-byte load per row and
+// the four weights), so that every row's stream and the weights are read
+// with wide coalesced loads and many bytes are in flight per thread.  The
+// weights are read once per row block: more rows per workgroup read them
+// fewer times.  Per thread the terms of a row are added in sample order;
+// the block sum and the chunk order then fix the rest of the order.
+constexpr int kRowsPerWg = 16;
 
 __global__ __launch_bounds__(256) void update_kernel(const DevParams p, const Buffers b, int R,
                                                      int nch, int chunk) {
@@ -780,11 +787,30 @@ __global__ __launch_bounds__(256) void update_kernel(const DevParams p, const Bu
 #pragma unroll
     for (int rr = 0; rr < kRowsPerWg; ++rr) acc[rr] = 0.0;
     const int kend = min(p.K, (c + 1) * chunk);
-    for (int k = c * chunk + threadIdx.x; k < kend; k += kBlock) {
-      const double e = b.E[k] * b.scale[k >> p.wg_shift];
+    // k is a multiple of four below K <= Ks (a multiple of 256), so the four
+    // eps entries stay inside the padded row; weights past K are zero
+    // (branch free, so that all the step's loads are issued together: rows
+    // past R read row R - 1 and are never stored, indices past the chunk
+    // read its last sample with zero weight)
+    for (int k = c * chunk + 4 * threadIdx.x; k < kend; k += 4 * kBlock) {
+      double e[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kq = min(k + q, kend - 1);
+        const double w = b.E[kq] * b.scale[kq >> p.wg_shift];
+        e[q] = k + q < kend ? w : 0.0;
+      }
+      float4 v[kRowsPerWg];
 #pragma unroll
       for (int rr = 0; rr < kRowsPerWg; ++rr)
-        if (r0 + rr < R) acc[rr] += e * (double)b.eps[(size_t)(r0 + rr) * p.Ks + k];
+        v[rr] = *reinterpret_cast<const float4*>(b.eps + (size_t)min(r0 + rr, R - 1) * p.Ks + k);
+#pragma unroll
+      for (int rr = 0; rr < kRowsPerWg; ++rr) {
+        acc[rr] += e[0] * (double)v[rr].x;
+        acc[rr] += e[1] * (double)v[rr].y;
+        acc[rr] += e[2] * (double)v[rr].z;
+        acc[rr] += e[3] * (double)v[rr].w;
+      }
     }
 #pragma unroll
     for (int rr = 0; rr < kRowsPerWg; ++rr) {
