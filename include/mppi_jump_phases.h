@@ -27,6 +27,12 @@ extern "C" {
  * error. */
 int mppi_phase_read(unsigned long long* out, size_t count);
 
+/* Batched form: the start and end timestamps of every tile of the last
+ * grid-launched batch kernel, [tile][2] for the first 8192 tiles (in the
+ * order of the tile list).  count >= 8192 * 2; errors as above. */
+#define MPPI_PHASE_TILES 8192
+int mppi_phase_read_tiles(unsigned long long* out, size_t count);
+
 #ifdef __cplusplus
 }
 #endif

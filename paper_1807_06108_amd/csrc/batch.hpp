@@ -83,9 +83,11 @@ template <bool WS, int MASK>
 __global__ __launch_bounds__(256) void batch_rollout_kernel(const BatchDesc* __restrict__ descs,
                                                             const BatchTile* __restrict__ tiles,
                                                             int shift) {
+  MPPI_TILE_MARK(blockIdx.x, 0);
   const BatchTile tl = tiles[blockIdx.x];
   const BatchDesc& d = descs[tl.ctl];
   batch_tile<WS, MASK>(d, d.x0, batch_shift(d, shift), tl.wg);
+  MPPI_TILE_MARK(blockIdx.x, 1);
 }
 
 // Work queue of the persistent launch: the next tile to take and the number

@@ -133,8 +133,9 @@ __device__ __forceinline__ void acquire_fence() { __builtin_amdgcn_fence(__ATOMI
 // mod kPhaseLaunches).  Slots: 0 workgroup start, 1 rollout done (costs
 // known), 2 partials stored, 3 arrival counted, 4 combine done and 5
 // epilogue done (the last workgroup only), 6 one for the last workgroup,
-// else zero, 7 the consumer's first chunk ready, 8 acquire done and 9
-// statistics combined (the last workgroup).
+// else zero, 7 the consumer's first chunk ready, 8 acquire done (the last
+// workgroup).  The batched grid launch also records each tile's start and
+// end.
 #ifdef MPPI_PHASE_STAMPS
 constexpr int kPhaseSlots = 16, kPhaseLaunches = 8, kPhaseMaxWg = 256;
 __device__ unsigned long long g_phase[kPhaseLaunches * kPhaseMaxWg * kPhaseSlots];
@@ -146,7 +147,16 @@ __device__ __forceinline__ void phase_mark(uint64_t it, int wg, int nwg, int slo
 #define MPPI_PHASE(it, wg, nwg, slot) \
   phase_mark((it), (wg), (nwg), (slot), __builtin_amdgcn_s_memrealtime())
 #define MPPI_PHASE_VALUE(it, wg, nwg, slot, v) phase_mark((it), (wg), (nwg), (slot), (v))
+// Batched form: start and end of every tile of the last launch (thread 0).
+constexpr int kPhaseTiles = 8192;
+__device__ unsigned long long g_phase_tiles[kPhaseTiles * 2];
+#define MPPI_TILE_MARK(tile, slot)                          \
+  do {                                                      \
+    if (threadIdx.x == 0 && (tile) < kPhaseTiles)           \
+      g_phase_tiles[(tile) * 2 + (slot)] = __builtin_amdgcn_s_memrealtime(); \
+  } while (0)
 #else
+#define MPPI_TILE_MARK(tile, slot) ((void)0)
 #define MPPI_PHASE(it, wg, nwg, slot) ((void)0)
 #define MPPI_PHASE_VALUE(it, wg, nwg, slot, v) ((void)0)
 #endif

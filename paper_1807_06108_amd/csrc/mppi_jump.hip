@@ -1498,12 +1498,20 @@ int mppi_jump_profile_read(mppi_jump_ctx* ctx, double* total_ms, int64_t* launch
 #ifdef MPPI_PHASE_STAMPS
 #include "../../include/mppi_jump_phases.h"
 static_assert(mppi::kPhaseLaunches == MPPI_PHASE_LAUNCHES && mppi::kPhaseMaxWg == MPPI_PHASE_MAX_WG &&
-                  mppi::kPhaseSlots == MPPI_PHASE_SLOTS,
+                  mppi::kPhaseSlots == MPPI_PHASE_SLOTS && mppi::kPhaseTiles == MPPI_PHASE_TILES,
               "record layout of the phase hook");
 extern "C" int mppi_phase_read(unsigned long long* out, size_t count) {
   const size_t n = sizeof(mppi::g_phase) / sizeof(mppi::g_phase[0]);
   if (!out || count < n) return MPPI_EINVAL;
   return hipMemcpyFromSymbol(out, HIP_SYMBOL(mppi::g_phase), sizeof(mppi::g_phase)) == hipSuccess
+             ? MPPI_OK
+             : MPPI_EDEVICE;
+}
+extern "C" int mppi_phase_read_tiles(unsigned long long* out, size_t count) {
+  const size_t n = sizeof(mppi::g_phase_tiles) / sizeof(mppi::g_phase_tiles[0]);
+  if (!out || count < n) return MPPI_EINVAL;
+  return hipMemcpyFromSymbol(out, HIP_SYMBOL(mppi::g_phase_tiles), sizeof(mppi::g_phase_tiles)) ==
+                 hipSuccess
              ? MPPI_OK
              : MPPI_EDEVICE;
 }

@@ -26,6 +26,14 @@ the gap from the end of one launch to the first workgroup start of the
 next.
 
     python -m paper_1807_06108_amd.phase_profile --workload cartpole_mpc
+
+With --batched N it profiles instead the batched form's grid launch over N
+mixed controllers (random_controllers, lane schedule): each tile's start and
+end, hence how many tiles are resident over the tick, the mean of that over
+the tick, the tail where it falls below 90 % of its peak, and each model's
+tile time per horizon step.
+
+    python -m paper_1807_06108_amd.phase_profile --batched 256
 """
 
 import argparse
@@ -34,7 +42,7 @@ import sys
 
 import numpy as np
 
-SLOTS, LAUNCHES, MAX_WG = 16, 8, 256
+SLOTS, LAUNCHES, MAX_WG, TILES = 16, 8, 256, 8192
 TICK_US = 0.01  # the real-time counter runs at 100 MHz
 
 
@@ -45,6 +53,8 @@ def main(argv=None):
                     help="iterations per control step (default: 5 for cartpole_mpc, else 3)")
     ap.add_argument("--reps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--batched", type=int, default=0,
+                    help="profile the batched grid launch over this many controllers instead")
     args = ap.parse_args(argv)
 
     # torch first: the library then binds to the HIP runtime torch loaded
@@ -56,6 +66,8 @@ def main(argv=None):
     L = native.lib()
     L.mppi_phase_read.restype = ctypes.c_int
     L.mppi_phase_read.argtypes = [ctypes.c_void_p, ctypes.c_size_t]
+    if args.batched:
+        return batched(args, L, torch)
 
     cfg = dict(workloads.PRESETS[args.workload](), schedule=native.C["MPPI_SCHED_WAVE_SPECIALISED"])
     iters = args.iters or (5 if args.workload == "cartpole_mpc" else 3)
@@ -119,6 +131,68 @@ def main(argv=None):
         start.mean(), loop.mean(), pub.mean(), arr.mean(), acq.mean(), comb.mean(), tail.mean(),
         gap.mean() if len(gap) else float("nan"), total))
     return 0
+
+
+def batched(args, L, torch):
+    """Tile timeline of the batched form's grid launch."""
+    from . import autotune, workloads
+    L.mppi_phase_read_tiles.restype = ctypes.c_int
+    L.mppi_phase_read_tiles.argtypes = [ctypes.c_void_p, ctypes.c_size_t]
+    cset = workloads.random_controllers(args.batched, seed=42)
+    cfgs = [c for c, _ in cset]
+    states = [torch.tensor(x, device="cuda") for _, x in cset]
+    _, b = autotune.make_batch(cfgs, states, (autotune.LANE, autotune.GRID, False))
+    for _ in range(5):
+        b.step(iters=1, shift=True)
+    torch.cuda.synchronize()
+    buf = np.zeros(TILES * 2, dtype=np.uint64)
+    spans, means, tails, ideal, per_step = [], [], [], [], {1: [], 2: []}
+    order = tile_order(cfgs)
+    if len(order) > TILES:
+        raise SystemExit("at most %d tiles are recorded" % TILES)
+    for _ in range(args.reps):
+        b.step(iters=1, shift=True)
+        torch.cuda.synchronize()
+        rc = L.mppi_phase_read_tiles(buf.ctypes.data, buf.size)
+        if rc != 0:
+            raise RuntimeError("mppi_phase_read_tiles: %d" % rc)
+        r = buf.reshape(TILES, 2)[:len(order)].astype(np.int64)
+        st = (r[:, 0] - r[:, 0].min()) * TICK_US
+        en = (r[:, 1] - r[:, 0].min()) * TICK_US
+        span = en.max()
+        grid = np.linspace(0.0, span, 201)[1:-1]
+        conc = np.array([((st <= t) & (en > t)).sum() for t in grid])
+        spans.append(span)
+        means.append((en - st).sum() / span)
+        tails.append(span * (conc < 0.9 * conc.max()).mean())
+        ideal.append((en - st).sum() / conc.max())
+        dur = en - st
+        for d in (1, 2):
+            m = np.array([cfgs[c]["dynamics"] == d for c in order])
+            T = np.array([cfgs[c]["T"] for c in order])
+            per_step[d].append(np.median(dur[m] / T[m]))
+        peak = conc.max()
+    work = sum(c["K"] * c["T"] for c in cfgs)
+    print("# Tile timeline of the batched grid launch: %d controllers (random_controllers, seed 42, "
+          "lane schedule), %d tiles, %.3g sample-steps per tick\n" % (len(cfgs), len(order), work))
+    print("Median over %d ticks (us; tile start and end by thread 0 of each tile).\n" % args.reps)
+    print("| tick span | peak resident tiles | mean resident tiles | summed tile time / peak "
+          "| time below 90 % of peak | cartpole tile time per step | quadrotor tile time per step |")
+    print("|---|---|---|---|---|---|---|")
+    print("| %.1f | %d | %.1f | %.1f | %.1f | %.3f | %.3f |" % (
+        np.median(spans), peak, np.median(means), np.median(ideal), np.median(tails),
+        np.median(per_step[1]), np.median(per_step[2])))
+    b.close()
+    return 0
+
+
+def tile_order(cfgs):
+    """Controller of every tile in launch order: controllers longest first
+    (tile cost K-independent per tile: T times the model's issue slots per
+    sample-step), each with its ceil(K / 256) lane-schedule tiles."""
+    cost = {0: 184, 1: 216, 2: 534}
+    idx = sorted(range(len(cfgs)), key=lambda i: -cfgs[i]["T"] * cost[cfgs[i]["dynamics"]])
+    return [i for i in idx for _ in range((cfgs[i]["K"] + 255) // 256)]
 
 
 if __name__ == "__main__":
