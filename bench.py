@@ -395,13 +395,15 @@ def serving_measure(rate, seconds, warm, n_ctl=1024, seed=4):
                                offered_per_s=b_rate, hbm_cap_gb=bounded / 2**30,
                                workspaces_gb=total / 2**30)
     cap = {}
-    for name, backend, schedule, offered in (("pool_lane", "pool", 1, 250e3),
+    for name, backend, schedule, offered in (("pool_lane", "pool", 1, 300e3),
                                              ("pool_ws", "pool", 2, 250e3),
                                              ("plain", "plain", sched, 40e3)):
         progress("serving capacity: %s" % name)
         r = run(backend, schedule, offered, 1.0, 0.5)
         cap[name] = {"offered_per_s": offered, "requests_per_s": r["requests_per_s"],
-                     "rollout_steps_per_s": r["rollout_steps_per_s"]}
+                     "rollout_steps_per_s": r["rollout_steps_per_s"],
+                     "mean_tick_requests": r["mean_tick_requests"],
+                     "latency_p50_ms": r["latency_ms"]["p50"]}
     out["capacity"] = cap
     return out
 
