@@ -231,7 +231,7 @@ __device__ __forceinline__ void epilogue_publish(const DevParams& p, const Buffe
           const float4* row =
               reinterpret_cast<const float4*>(tile + (size_t)(base + i) * tstride + q * SQ);
           const double* ew = e_lds + q * SQ;
-#pragma unroll
+#pragma unroll 2
           for (int j = 0; j < SQ / 4; ++j) {
             const float4 v = row[j];
             acc += ew[4 * j] * (double)v.x;
