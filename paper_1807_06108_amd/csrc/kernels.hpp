@@ -802,18 +802,27 @@ __global__ __launch_bounds__(256) void update_kernel(const DevParams p, const Bu
     // (branch free, so that all the step's loads are issued together: rows
     // past R read row R - 1 and are never stored, indices past the chunk
     // read its last sample with zero weight)
-    for (int k = c * chunk + 4 * threadIdx.x; k < kend; k += 4 * kBlock) {
-      double e[4];
+    // The next step's loads are issued before this step's sums.
+    auto load = [&](int k, double* e, float4* v) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int kq = min(k + q, kend - 1);
         const double w = b.E[kq] * b.scale[kq >> p.wg_shift];
         e[q] = k + q < kend ? w : 0.0;
       }
-      float4 v[kRowsPerWg];
 #pragma unroll
       for (int rr = 0; rr < kRowsPerWg; ++rr)
         v[rr] = *reinterpret_cast<const float4*>(b.eps + (size_t)min(r0 + rr, R - 1) * p.Ks + k);
+    };
+    int k = c * chunk + 4 * threadIdx.x;
+    double e[4];
+    float4 v[kRowsPerWg];
+    if (k < kend) load(k, e, v);
+    for (; k < kend; k += 4 * kBlock) {
+      double en[4];
+      float4 vn[kRowsPerWg];
+      const int kn = k + 4 * kBlock;
+      if (kn < kend) load(kn, en, vn);
 #pragma unroll
       for (int rr = 0; rr < kRowsPerWg; ++rr) {
         acc[rr] += e[0] * (double)v[rr].x;
@@ -821,6 +830,10 @@ __global__ __launch_bounds__(256) void update_kernel(const DevParams p, const Bu
         acc[rr] += e[2] * (double)v[rr].z;
         acc[rr] += e[3] * (double)v[rr].w;
       }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) e[q] = en[q];
+#pragma unroll
+      for (int rr = 0; rr < kRowsPerWg; ++rr) v[rr] = vn[rr];
     }
 #pragma unroll
     for (int rr = 0; rr < kRowsPerWg; ++rr) {
