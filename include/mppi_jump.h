@@ -184,7 +184,13 @@ int mppi_jump_init(const mppi_jump_config* cfg, void* d_workspace, size_t ws_byt
  * the state d_x0 ([n] fp32 device), updating U in place.  Each iteration
  * draws fresh noise (its own iteration index).  If every S~_k of an
  * iteration is non-finite, that iteration leaves U unchanged and records
- * MPPI_ENONFINITE in the statistics (read with MPPI_ITEM_STATS). */
+ * MPPI_ENONFINITE in the statistics (read with MPPI_ITEM_STATS).
+ * With at most 512 rollout workgroups the update of eqs. (36)-(37) runs in
+ * the rollout kernel's epilogue (one kernel per iteration).  Beyond that,
+ * the one-sample-per-lane schedule publishes each workgroup's weighted
+ * perturbation sums from its epilogue and a second kernel combines them;
+ * the wave-specialised schedule, and any context with debug_dump, runs the
+ * staged pair (mppi_jump_rollout, mppi_jump_update). */
 int mppi_jump_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, void* stream);
 
 /* One MPC control step (Algorithm 1 loop body, Sec. V): `iters` >= 1

@@ -30,7 +30,13 @@ struct alignas(128) WgPartial {
   int32_t nfin;  // number of finite S_k
 };
 
+// Arrival counters: [0] rollout arrivals, [1] update arrivals, then one per
+// block of kPartRows rows for the deferred update (partial_update_kernel).
 constexpr int kCounters = 2;
+constexpr int kPartRows = 64;
+__host__ __device__ constexpr int counter_count(int R) {
+  return kCounters + (R + kPartRows - 1) / kPartRows;
+}
 
 struct DevParams {
   int K, T, Ks, n_th;
@@ -65,7 +71,7 @@ struct Buffers {
   double* upart;      // [T*m][nch]   chunk partials of update_kernel
   double* wpart;      // [nwg][T*m]   workgroup partials of the fused epilogue
   mppi_jump_stats* stats;
-  uint32_t* counters; // [kCounters]: [0] rollout arrivals, [1] update arrivals
+  uint32_t* counters; // [counter_count(T*m)] arrival counters
   float* dbg_zD;      // [K][T][m]
   int32_t* dbg_N;     // [K][T]
   float* dbg_zJ;      // [K][T][q]
@@ -181,7 +187,15 @@ __device__ unsigned long long g_phase_tiles[kPhaseTiles * 2];
 // of its SPW samples at tile[r tstride ..] (on chip, or its columns of the
 // HBM array).  part / wpart: where this workgroup's partials go (row r of
 // workgroup wg at wpart[wg R + r]).
-template <int SPW, bool FUSED, int NT>
+// RB (256-sample workgroups): 0, the tile sums as described below; else
+// each wavefront takes every fourth row, each lane the four consecutive
+// samples 4 lane .. 4 lane + 3 with their weights held in registers, RB rows
+// in flight at once (one float4 load per lane and row), each row's 64 lane
+// sums added by a wavefront reduction.  The deferred-update form uses it:
+// its tiles are re-read from HBM by every resident workgroup at about the
+// same time, and the quarter layout's loads (two in flight, each with four
+// fp64 weights) leave that latency bound.
+template <int SPW, bool FUSED, int NT, int RB = 0>
 __device__ __forceinline__ void epilogue_publish(const DevParams& p, const Buffers& b, double Sd,
                                                  bool active, int R, int wg, const float* tile,
                                                  int tstride, WgPartial* part, double* wpart) {
@@ -214,7 +228,36 @@ __device__ __forceinline__ void epilogue_publish(const DevParams& p, const Buffe
     eta_wg = block_sum<NW>(e, lds);
     nfin = block_sum<NW>(fin ? 1.0 : 0.0, lds);  // its barriers publish e_lds
   }
-  if constexpr (FUSED) {
+  if constexpr (FUSED && RB > 0) {
+    static_assert(SPW == 256 && NT == 256, "four samples per lane, four wavefronts");
+    double w4[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) w4[i] = e_lds[4 * lane + i];
+    for (int base = 0; base < R; base += kStageRows) {
+      const int nrow = min(kStageRows, R - base);
+      for (int i0 = wave; i0 < nrow; i0 += 4 * RB) {
+        float4 v[RB];
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+          const int i = min(i0 + 4 * j, nrow - 1);  // rows past the block: its last, unused
+          v[j] = reinterpret_cast<const float4*>(tile + (size_t)(base + i) * tstride)[lane];
+        }
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+          double a = w4[0] * (double)v[j].x;
+          a += w4[1] * (double)v[j].y;
+          a += w4[2] * (double)v[j].z;
+          a += w4[3] * (double)v[j].w;
+          a = wave_sum(a);
+          if (lane == 0 && i0 + 4 * j < nrow) stage[i0 + 4 * j] = a;
+        }
+      }
+      __syncthreads();
+      if (wave == 0)
+        for (int i = lane; i < nrow; i += 64) wpart[(size_t)wg * R + base + i] = stage[i];
+      __syncthreads();
+    }
+  } else if constexpr (FUSED) {
     // the workgroup's own eps tile (written earlier in this kernel by its
     // threads, visible after the barriers above): row r is reduced by four
     // consecutive threads over a quarter of the samples each, in sample
@@ -484,8 +527,12 @@ __device__ __forceinline__ void record_stats(const Buffers& b, const Combined& c
 // The one-iteration epilogue: publish, then the last workgroup to arrive
 // combines, applies the update (FUSED) and, when sh.on, the shift, records
 // the statistics and advances the iteration counter (FUSED).
+// DEFER (with FUSED): the weighted tile sums are published as in the fused
+// form, but the last workgroup forms only the statistics and the rescales
+// (stored to b.scale); partial_update_kernel then applies the update.  For
+// rollouts with too many workgroups for one workgroup to combine.
 // wg / nwg: this workgroup's index among the nwg workgroups of its controller.
-template <int SPW, bool FUSED, int NT = kBlock>
+template <int SPW, bool FUSED, int NT = kBlock, bool DEFER = false, int RB = 8>
 __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffers& b, double Sd,
                                                  bool active, int R, const ShiftArgs sh, int wg,
                                                  int nwg, const float* tile, int tstride) {
@@ -495,7 +542,8 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
   const uint64_t it = b.stats->iteration;
 #endif
   MPPI_PHASE(it, wg, nwg, 1);
-  epilogue_publish<SPW, FUSED, NT>(p, b, Sd, active, R, wg, tile, tstride, b.part, b.wpart);
+  epilogue_publish<SPW, FUSED, NT, DEFER ? RB : 0>(p, b, Sd, active, R, wg, tile, tstride, b.part,
+                                                   b.wpart);
   MPPI_PHASE(it, wg, nwg, 2);
   if (wave == 0) {
     release_fence();
@@ -510,9 +558,10 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
   if (!is_last) return;
   acquire_fence();
   MPPI_PHASE(it, wg, nwg, 8);
-  const Combined c = epilogue_combine<FUSED, NT>(p, b.part, b.wpart, nwg, R, b.U, b.U, b.scale);
+  constexpr bool UPDATE = FUSED && !DEFER;
+  const Combined c = epilogue_combine<UPDATE, NT>(p, b.part, b.wpart, nwg, R, b.U, b.U, b.scale);
   MPPI_PHASE(it, wg, nwg, 4);
-  if constexpr (FUSED) {
+  if constexpr (UPDATE) {
     if (sh.on) {
       __syncthreads();  // the updated rows are visible to the whole block
       epilogue_shift<NT>(sh, b.U, b.U, R);
@@ -520,7 +569,7 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
   }
   MPPI_PHASE(it, wg, nwg, 5);
   if (threadIdx.x == 0) {
-    record_stats(b, c, b.stats->iteration + 1, FUSED);
+    record_stats(b, c, b.stats->iteration + 1, UPDATE);
     b.counters[0] = 0u;
   }
 }
@@ -667,8 +716,10 @@ __device__ __forceinline__ float state_free_cost(const DevParams& p, const Const
 // and update_kernel follows.
 // One workgroup (tile wg of nwg) of the one-sample-per-lane rollout.  U is
 // not restrict-qualified: in the fused form the last workgroup writes the
-// same array (through b.U) while the kernel runs.
-template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL = false>
+// same array (through b.U) while the kernel runs.  DEFER: the epilogue's
+// deferred-update form (rollout_epilogue).
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL = false,
+          bool DEFER = false>
 __device__ __forceinline__ void rollout_lane_tile(const DevParams& p, const Buffers& b,
                                                   const float* __restrict__ x0,
                                                   const float* U, int R,
@@ -751,17 +802,23 @@ __device__ __forceinline__ void rollout_lane_tile(const DevParams& p, const Buff
   if constexpr (Md::CAN_CRASH) qf += crashed ? p.pen : 0.f;
   const double Sd = S.S + (double)qf;
   if (active) b.S[k] = Sd;
-  rollout_epilogue<kBlock, FUSED>(p, b, Sd, active, R, sh, wg, nwg,
-                                  b.eps + (size_t)wg * kBlock, p.Ks);
+  // rows of the deferred form's tile sums in flight per wavefront: four
+  // keep the one-channel kernels at their rollout's 68 registers (eight
+  // take 88 and cost occupancy: cartpole K=2^20, T=100 0.517 -> 0.532 ms
+  // per iteration); the 12-state model's rollout holds 120, which sixteen
+  // rows reuse
+  constexpr int RB = M > 1 ? 16 : 4;
+  rollout_epilogue<kBlock, FUSED, kBlock, DEFER, RB>(p, b, Sd, active, R, sh, wg, nwg,
+                                                     b.eps + (size_t)wg * kBlock, p.Ks);
 }
 
-template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL>
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL, bool DEFER = false>
 __global__ __launch_bounds__(256) void rollout_kernel(const DevParams p, const Buffers b,
                                                       const float* __restrict__ x0,
                                                       const float* U, int R,
                                                       const ShiftArgs sh) {
-  rollout_lane_tile<DYN, JUMPS, DEBUG, FORM, FUSED, FULL>(p, b, x0, U, R, sh, blockIdx.x,
-                                                         gridDim.x);
+  rollout_lane_tile<DYN, JUMPS, DEBUG, FORM, FUSED, FULL, DEFER>(p, b, x0, U, R, sh, blockIdx.x,
+                                                                gridDim.x);
 }
 
 // Statistics of caller-provided costs (mppi_jump_set of S), with the
@@ -863,6 +920,82 @@ __global__ __launch_bounds__(256) void update_kernel(const DevParams p, const Bu
   }
 }
 
+// Deferred update, eq. (36) from the workgroup partials of eq. (37):
+// U[r] += alpha / eta * sum_wg scale_wg P[wg][r], for rollouts with too
+// many workgroups for the last one to combine (the rollout's epilogue has
+// published P and stored the rescales scale_wg).  Workgroup (rb, c) takes
+// the kPartRows rows of block rb over the partials of chunk c: wavefront q
+// sums partials q, q + 4, ... of the chunk in order (each a coalesced load
+// of the block's rows; kPartLoads of them in flight per thread), and the four
+// wavefront sums, added as (s0 + s1) + (s2 + s3), go to upart[r][c].  The
+// last workgroup of a row block to arrive adds its rows' chunk sums in chunk
+// order (four contiguous runs of chunks, one per wavefront, combined the
+// same way) and updates U; the one of block 0 advances the iteration counter.
+constexpr int kPartLoads = 16;
+constexpr int kPartMaxChunks = 64;
+
+__global__ __launch_bounds__(256) void partial_update_kernel(const DevParams p, const Buffers b,
+                                                             int R, int nwg, int nch, int chunk) {
+  __shared__ double sums[4][kPartRows];
+  __shared__ int is_last;
+  const mppi_jump_stats st = *b.stats;
+  const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int rb = blockIdx.x, c = blockIdx.y;
+  const int r = rb * kPartRows + lane;
+  const bool live = r < R;
+  const int rr = min(r, R - 1);  // rows past R read row R - 1 and are never stored
+  const bool ok = st.status == MPPI_OK;
+  if (ok) {
+    const int j0 = c * chunk, j1 = min(nwg, j0 + chunk);
+    double acc = 0.0;
+    for (int jb = j0 + q; jb < j1; jb += 4 * kPartLoads) {
+      double w[kPartLoads], sc[kPartLoads];
+#pragma unroll
+      for (int i = 0; i < kPartLoads; ++i) {
+        const int j = min(jb + 4 * i, j1 - 1);
+        w[i] = b.wpart[(size_t)j * R + rr];
+        sc[i] = b.scale[j];
+      }
+#pragma unroll
+      for (int i = 0; i < kPartLoads; ++i)
+        if (jb + 4 * i < j1) acc += sc[i] * w[i];
+    }
+    sums[q][lane] = acc;
+    __syncthreads();
+    if (q == 0 && live)
+      b.upart[(size_t)r * nch + c] = (sums[0][lane] + sums[1][lane]) + (sums[2][lane] + sums[3][lane]);
+  }
+  if (q == 0) {
+    release_fence();  // wavefront 0's chunk sums before its arrival
+    if (lane == 0) is_last = atomicAdd(&b.counters[kCounters + rb], 1u) == (uint32_t)nch - 1;
+  }
+  __syncthreads();
+  if (!is_last) return;
+  acquire_fence();
+  if (ok) {
+    const int L = (nch + 3) / 4;  // at most kPartMaxChunks / 4
+    const int c0 = q * L, c1 = min(nch, c0 + L);
+    double v[kPartMaxChunks / 4];
+#pragma unroll
+    for (int i = 0; i < kPartMaxChunks / 4; ++i)
+      v[i] = c0 + i < c1 ? b.upart[(size_t)rr * nch + c0 + i] : 0.0;
+    double d = 0.0;
+#pragma unroll
+    for (int i = 0; i < kPartMaxChunks / 4; ++i)
+      if (c0 + i < c1) d += v[i];
+    sums[q][lane] = d;
+    __syncthreads();
+    if (q == 0 && live) {
+      const double tot = (sums[0][lane] + sums[1][lane]) + (sums[2][lane] + sums[3][lane]);
+      b.U[r] = (float)((double)b.U[r] + (double)p.alpha / st.eta * tot);
+    }
+  }
+  if (threadIdx.x == 0) {
+    b.counters[kCounters + rb] = 0u;
+    if (rb == 0) b.stats->iteration = st.iteration + 1;
+  }
+}
+
 // ------------------------------------------------------------------ misc
 __global__ void init_kernel(Buffers b, const float* __restrict__ U0, int R, int m,
                             float4 u_init, uint64_t start_iteration) {
@@ -878,21 +1011,21 @@ __global__ void init_kernel(Buffers b, const float* __restrict__ U0, int R, int 
     b.stats->status = MPPI_OK;
     b.stats->n_finite = 0;
     b.stats->iteration = start_iteration;
-    for (int i = 0; i < kCounters; ++i) b.counters[i] = 0u;
+    for (int i = 0; i < counter_count(R); ++i) b.counters[i] = 0u;
   }
 }
 
 // Statistics, iteration counter and arrival counters of a workspace reset,
 // leaving U alone (the no-allocation control step, whose sequence belongs
 // to the caller).
-__global__ void stats_init_kernel(Buffers b, uint64_t start_iteration) {
+__global__ void stats_init_kernel(Buffers b, int R, uint64_t start_iteration) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     b.stats->rho = 0.0;
     b.stats->eta = 0.0;
     b.stats->status = MPPI_OK;
     b.stats->n_finite = 0;
     b.stats->iteration = start_iteration;
-    for (int i = 0; i < kCounters; ++i) b.counters[i] = 0u;
+    for (int i = 0; i < counter_count(R); ++i) b.counters[i] = 0u;
   }
 }
 

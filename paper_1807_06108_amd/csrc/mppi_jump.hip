@@ -180,6 +180,9 @@ struct Layout {
   bool ws;     // wave-specialised schedule (64 samples per workgroup)
   int spw;     // samples per rollout workgroup
   bool fused;
+  // one-sample-per-lane rollouts with more workgroups than the fused form
+  // combines: tile sums published, update by partial_update_kernel
+  bool deferred;
   bool eps_lds;  // fused wave-specialised iterations keep the perturbations on chip
   size_t U, eps, S, E, part, scale, upart, wpart, stats, counters, W, zD, N, zJ, total;
 };
@@ -218,9 +221,10 @@ Layout make_layout(const mppi_jump_config* c, int m, int q) {
     default: fits = ws_eps_fits<MPPI_DYN_QUADROTOR>(L.R); break;
   }
   L.eps_lds = L.ws && L.fused && !c->debug_dump && fits;
-  L.wpart = take(L.fused ? (size_t)L.nwg * L.R * 8 : 0);
+  L.deferred = !L.fused && !L.ws && !c->debug_dump;
+  L.wpart = take(L.fused || L.deferred ? (size_t)L.nwg * L.R * 8 : 0);
   L.stats = take(sizeof(mppi_jump_stats));
-  L.counters = take(kCounters * sizeof(uint32_t));
+  L.counters = take((size_t)counter_count(L.R) * sizeof(uint32_t));
   L.W = take(K * 8);
   if (c->debug_dump) {
     L.zD = take(K * T * m * 4);
@@ -360,7 +364,7 @@ void bind_context(mppi_jump_ctx* ctx, const mppi_jump_config* cfg, int n, int m,
   b.part = reinterpret_cast<WgPartial*>(base + L.part);
   b.scale = reinterpret_cast<double*>(base + L.scale);
   b.upart = reinterpret_cast<double*>(base + L.upart);
-  b.wpart = L.fused ? reinterpret_cast<double*>(base + L.wpart) : nullptr;
+  b.wpart = L.fused || L.deferred ? reinterpret_cast<double*>(base + L.wpart) : nullptr;
   b.stats = reinterpret_cast<mppi_jump_stats*>(base + L.stats);
   b.counters = reinterpret_cast<uint32_t*>(base + L.counters);
   ctx->W = reinterpret_cast<double*>(base + L.W);
@@ -405,6 +409,14 @@ int launch_rollout_t(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, const S
   ctx->eps_stored = !(FUSED && !DEBUG && ctx->L.eps_lds);
   if constexpr (FUSED && !DEBUG) {
     if (ctx->L.eps_lds) return launch_ws<DYN, JUMPS, DEBUG, FORM, FUSED, FULL, true>(ctx, x0, s, sh);
+  }
+  if constexpr (FUSED && !DEBUG) {
+    if (ctx->L.deferred) {
+      rollout_kernel<DYN, JUMPS, DEBUG, FORM, FUSED, FULL, true>
+          <<<dim3(ctx->L.nwg), dim3(kBlock), 0, s>>>(ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R, sh);
+      LAUNCH_CHECK("rollout_kernel");
+      return MPPI_OK;
+    }
   }
   if (ctx->L.ws) {
     return launch_ws<DYN, JUMPS, DEBUG, FORM, FUSED, FULL, false>(ctx, x0, s, sh);
@@ -494,6 +506,19 @@ int launch_update(mppi_jump_ctx* ctx, hipStream_t s) {
   const dim3 grid((ctx->L.R + kRowsPerWg - 1) / kRowsPerWg, ctx->L.nch), block(kBlock);
   update_kernel<<<grid, block, 0, s>>>(ctx->p, ctx->b, ctx->L.R, ctx->L.nch, ctx->L.chunk);
   LAUNCH_CHECK("update_kernel");
+  return MPPI_OK;
+}
+
+// The update after a deferred-form rollout: the L.nch chunks of workgroup
+// partials (upart holds R x L.nch chunk sums) over row blocks of kPartRows.
+int launch_partial_update(mppi_jump_ctx* ctx, hipStream_t s) {
+  const int nch = ctx->L.nch, nwg = ctx->L.nwg;
+  if (nch < 1 || nch > kPartMaxChunks)
+    return fail(MPPI_EDEVICE, "deferred update over %d chunks (1..%d)", nch, kPartMaxChunks);
+  const dim3 grid((ctx->L.R + kPartRows - 1) / kPartRows, nch), block(kBlock);
+  partial_update_kernel<<<grid, block, 0, s>>>(ctx->p, ctx->b, ctx->L.R, nwg, nch,
+                                               (nwg + nch - 1) / nch);
+  LAUNCH_CHECK("partial_update_kernel");
   return MPPI_OK;
 }
 
@@ -614,10 +639,10 @@ int mppi_jump_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, void* s
       if (rb != MPPI_OK) return rb;
     }
     for (int i = 0; i < iters; ++i) {
-      int rc = launch_rollout(ctx, d_x0, s, ctx->L.fused, ShiftArgs{}, !span);
+      int rc = launch_rollout(ctx, d_x0, s, ctx->L.fused || ctx->L.deferred, ShiftArgs{}, !span);
       if (rc != MPPI_OK) return rc;
       if (!ctx->L.fused) {
-        rc = launch_update(ctx, s);
+        rc = ctx->L.deferred ? launch_partial_update(ctx, s) : launch_update(ctx, s);
         if (rc != MPPI_OK) return rc;
       }
       ctx->host_iteration += 1;
@@ -730,7 +755,7 @@ int mppi_jump_control_step_static(const mppi_jump_config* cfg, float* d_U, const
     const hipStream_t s = static_cast<hipStream_t>(stream);
     // statistics, iteration counter and arrival counters start afresh (a fill
     // kernel, not a memset node, so that the call can be captured)
-    stats_init_kernel<<<1, 64, 0, s>>>(ctx.b, cfg->start_iteration);
+    stats_init_kernel<<<1, 64, 0, s>>>(ctx.b, L.R, cfg->start_iteration);
     LAUNCH_CHECK("stats_init_kernel");
     return enqueue_control_step(&ctx, d_x0, iters, d_u0_out, stream);
   });
