@@ -25,7 +25,9 @@ The JSON line also carries
                    the capacity of each back end,
   saturation       the same rollout at a shape that fills the GPU (K=2^20,
                    lane schedule) per model: the kernel against its roofline
-                   where occupancy does not bound it,
+                   where occupancy does not bound it, and the whole iteration
+                   (its update a second kernel at this K) against the same
+                   peak,
   other_configs    the other single-GPU configurations, each with its value,
                    time per iteration, roofline and oracle timings: the single
                    cartpole iteration (K=256, T=50) and the quadrotor hover
@@ -278,7 +280,11 @@ def iteration_measure(name, calls, warmup, **over):
                          "traffic": measured_traffic(name) if not over else None,
                          "avg_launch_us": avg_roll_s * 1e6, "launches_timed": launches,
                          "slots_per_sample_step": ALG_SLOTS[dyn],
-                         "fp32_tflops": flops / 1e12, "fp32_frac": flops / FP32_PEAK}}
+                         "fp32_tflops": flops / 1e12, "fp32_frac": flops / FP32_PEAK,
+                         # the same slots over the whole iteration (every
+                         # kernel of it, wall clock): where the update runs
+                         # as a kernel of its own, this is the figure to read
+                         "iteration_frac": ALG_SLOTS[dyn] * K * T * calls / wall / VALU_PEAK_SLOTS}}
 
 
 def batched_measure(n_ctl, ticks, warmup, seed=42):

@@ -377,14 +377,21 @@ __device__ __forceinline__ Combined epilogue_combine(const DevParams& p, const W
     WgPartial q0{INFINITY, 0.0, 0};
     if (threadIdx.x < n) q0 = parts[threadIdx.x];
     double m = q0.nfin > 0 ? q0.rho : INFINITY;
+    // four partials' minima in flight at once (many partials: one memory
+    // round trip per four instead of one each)
+#pragma unroll 4
     for (int j = threadIdx.x + NT; j < n; j += NT) {
-      const WgPartial q = parts[j];
-      m = q.nfin > 0 ? fmin(m, q.rho) : m;
+      const double rj = parts[j].rho;
+      const int fj = parts[j].nfin;
+      m = fj > 0 ? fmin(m, rj) : m;
     }
     const double rho = block_min<NW>(m, lds);
     double eta = 0.0, cnt = 0.0;
+    // the next partial is loaded while this one's rescale is formed
+    WgPartial qn = q0;
     for (int j = threadIdx.x; j < n; j += NT) {
-      const WgPartial q = j < NT ? q0 : parts[j];
+      const WgPartial q = qn;
+      if (j + NT < n) qn = parts[j + NT];
       const double sc = (q.nfin > 0) ? exp(-(q.rho - rho) / p.lam_d) : 0.0;
       if (scale != nullptr) scale[j] = sc;
       if constexpr (FUSED) sc_lds[j] = sc;
@@ -945,7 +952,9 @@ __global__ __launch_bounds__(256) void partial_update_kernel(const DevParams p, 
   const bool live = r < R;
   const int rr = min(r, R - 1);  // rows past R read row R - 1 and are never stored
   const bool ok = st.status == MPPI_OK;
-  if (ok) {
+  {
+    // the loads do not wait for the status (they stay inside the partials
+    // either way); only the store does
     const int j0 = c * chunk, j1 = min(nwg, j0 + chunk);
     double acc = 0.0;
     for (int jb = j0 + q; jb < j1; jb += 4 * kPartLoads) {
@@ -962,7 +971,7 @@ __global__ __launch_bounds__(256) void partial_update_kernel(const DevParams p, 
     }
     sums[q][lane] = acc;
     __syncthreads();
-    if (q == 0 && live)
+    if (ok && q == 0 && live)
       b.upart[(size_t)r * nch + c] = (sums[0][lane] + sums[1][lane]) + (sums[2][lane] + sums[3][lane]);
   }
   if (q == 0) {
