@@ -191,10 +191,12 @@ __device__ unsigned long long g_phase_tiles[kPhaseTiles * 2];
 // each wavefront takes every fourth row, each lane the four consecutive
 // samples 4 lane .. 4 lane + 3 with their weights held in registers, RB rows
 // in flight at once (one float4 load per lane and row), each row's 64 lane
-// sums added by a wavefront reduction.  The deferred-update form uses it:
-// its tiles are re-read from HBM by every resident workgroup at about the
-// same time, and the quarter layout's loads (two in flight, each with four
-// fp64 weights) leave that latency bound.
+// sums added by a wavefront reduction (the order of a row's terms does not
+// depend on RB).  The one-sample-per-lane kernels use it: their tiles come
+// back from L2 or, in the deferred-update form, from HBM, and the quarter
+// layout's loads (two in flight, each with four fp64 weights) leave that
+// latency bound.  The wave-specialised kernels' 64-sample tiles keep the
+// quarter layout.
 template <int SPW, bool FUSED, int NT, int RB = 0>
 __device__ __forceinline__ void epilogue_publish(const DevParams& p, const Buffers& b, double Sd,
                                                  bool active, int R, int wg, const float* tile,
@@ -549,8 +551,8 @@ __device__ __forceinline__ void rollout_epilogue(const DevParams& p, const Buffe
   const uint64_t it = b.stats->iteration;
 #endif
   MPPI_PHASE(it, wg, nwg, 1);
-  epilogue_publish<SPW, FUSED, NT, DEFER ? RB : 0>(p, b, Sd, active, R, wg, tile, tstride, b.part,
-                                                   b.wpart);
+  epilogue_publish<SPW, FUSED, NT, SPW == 256 ? RB : 0>(p, b, Sd, active, R, wg, tile, tstride,
+                                                        b.part, b.wpart);
   MPPI_PHASE(it, wg, nwg, 2);
   if (wave == 0) {
     release_fence();
@@ -809,8 +811,8 @@ __device__ __forceinline__ void rollout_lane_tile(const DevParams& p, const Buff
   if constexpr (Md::CAN_CRASH) qf += crashed ? p.pen : 0.f;
   const double Sd = S.S + (double)qf;
   if (active) b.S[k] = Sd;
-  // rows of the deferred form's tile sums in flight per wavefront: four
-  // keep the one-channel kernels at their rollout's 68 registers (eight
+  // rows of the epilogue's tile sums in flight per wavefront: four keep
+  // the one-channel deferred kernels at their rollout's 68 registers (eight
   // take 88 and cost occupancy: cartpole K=2^20, T=100 0.517 -> 0.532 ms
   // per iteration); the 12-state model's rollout holds 120, which sixteen
   // rows reuse
