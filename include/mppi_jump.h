@@ -187,10 +187,9 @@ int mppi_jump_init(const mppi_jump_config* cfg, void* d_workspace, size_t ws_byt
  * MPPI_ENONFINITE in the statistics (read with MPPI_ITEM_STATS).
  * With at most 512 rollout workgroups the update of eqs. (36)-(37) runs in
  * the rollout kernel's epilogue (one kernel per iteration).  Beyond that,
- * the one-sample-per-lane schedule publishes each workgroup's weighted
- * perturbation sums from its epilogue and a second kernel combines them;
- * the wave-specialised schedule, and any context with debug_dump, runs the
- * staged pair (mppi_jump_rollout, mppi_jump_update). */
+ * each workgroup's epilogue publishes its weighted perturbation sums and a
+ * second kernel combines them; a context with debug_dump runs the staged
+ * pair (mppi_jump_rollout, mppi_jump_update) instead. */
 int mppi_jump_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, void* stream);
 
 /* One MPC control step (Algorithm 1 loop body, Sec. V): `iters` >= 1
@@ -245,11 +244,11 @@ int mppi_jump_shift(mppi_jump_ctx* ctx, float* u0_out, void* stream);
 /* Enqueue a copy of an item (MPPI_ITEM_*) into dst (device or host memory).
  * EINVAL if dst_bytes is smaller than the item; EUNSUPPORTED for a debug
  * item of a context created without debug_dump, and for MPPI_ITEM_EPS after
- * an iteration that kept its perturbations on chip: the fused
- * wave-specialised iteration (mppi_jump_step / mppi_jump_control_step with
- * at most 512 rollout workgroups) holds its tile of perturbations in LDS
- * until the update has used them and never stores them, when the tile fits
- * (T <= 496 for the one-channel models, T <= 108 for the quadrotor);
+ * an iteration that kept its perturbations on chip: the wave-specialised
+ * iteration of mppi_jump_step / mppi_jump_control_step (without debug_dump)
+ * holds its tile of perturbations in LDS until its weighted sums are formed
+ * and never stores them, when the tile fits (T <= 496 for the one-channel
+ * models, T <= 108 for the quadrotor);
  * every staged rollout (mppi_jump_rollout), unfused or lane-schedule
  * iteration, batch step and pool tick stores them.  MPPI_ITEM_W and
  * MPPI_ITEM_THRESH are computed at call time (W from the current S and

@@ -180,8 +180,8 @@ struct Layout {
   bool ws;     // wave-specialised schedule (64 samples per workgroup)
   int spw;     // samples per rollout workgroup
   bool fused;
-  // one-sample-per-lane rollouts with more workgroups than the fused form
-  // combines: tile sums published, update by partial_update_kernel
+  // rollouts with more workgroups than the fused form combines: tile sums
+  // published, update by partial_update_kernel
   bool deferred;
   bool eps_lds;  // fused wave-specialised iterations keep the perturbations on chip
   size_t U, eps, S, E, part, scale, upart, wpart, stats, counters, W, zD, N, zJ, total;
@@ -214,14 +214,15 @@ Layout make_layout(const mppi_jump_config* c, int m, int q) {
   L.scale = take((size_t)L.nwg * 8);
   L.upart = take((size_t)L.R * L.nch * 8);
   L.fused = L.nwg <= kFusedMaxWg;
+  L.deferred = !L.fused && !c->debug_dump;
+  const int per_cu = L.fused ? 1 : 2;
   bool fits = false;
   switch (c->dynamics) {
-    case MPPI_DYN_LINEAR: fits = ws_eps_fits<MPPI_DYN_LINEAR>(L.R); break;
-    case MPPI_DYN_CARTPOLE: fits = ws_eps_fits<MPPI_DYN_CARTPOLE>(L.R); break;
-    default: fits = ws_eps_fits<MPPI_DYN_QUADROTOR>(L.R); break;
+    case MPPI_DYN_LINEAR: fits = ws_eps_fits<MPPI_DYN_LINEAR>(L.R, per_cu); break;
+    case MPPI_DYN_CARTPOLE: fits = ws_eps_fits<MPPI_DYN_CARTPOLE>(L.R, per_cu); break;
+    default: fits = ws_eps_fits<MPPI_DYN_QUADROTOR>(L.R, per_cu); break;
   }
-  L.eps_lds = L.ws && L.fused && !c->debug_dump && fits;
-  L.deferred = !L.fused && !L.ws && !c->debug_dump;
+  L.eps_lds = L.ws && (L.fused || L.deferred) && !c->debug_dump && fits;
   L.wpart = take(L.fused || L.deferred ? (size_t)L.nwg * L.R * 8 : 0);
   L.stats = take(sizeof(mppi_jump_stats));
   L.counters = take((size_t)counter_count(L.R) * sizeof(uint32_t));
@@ -392,9 +393,10 @@ int raise_ws_lds_limit(const void* kern) {
   return MPPI_OK;
 }
 
-template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL, bool EPS_LDS>
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL, bool EPS_LDS,
+          bool DEFER = false>
 int launch_ws(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, const ShiftArgs& sh) {
-  const auto kern = rollout_ws_kernel<DYN, JUMPS, DEBUG, FORM, FUSED, FULL, EPS_LDS>;
+  const auto kern = rollout_ws_kernel<DYN, JUMPS, DEBUG, FORM, FUSED, FULL, EPS_LDS, DEFER>;
   static const int raised = raise_ws_lds_limit(reinterpret_cast<const void*>(kern));
   if (raised != MPPI_OK) return fail(raised, "%s", "the LDS limit of rollout_ws_kernel");
   const size_t lds = EPS_LDS ? ws_eps_lds_bytes<DYN>(ctx->L.R) : ws_lds_bytes<DYN>(ctx->L.R);
@@ -408,9 +410,12 @@ template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL>
 int launch_rollout_t(mppi_jump_ctx* ctx, const float* x0, hipStream_t s, const ShiftArgs& sh) {
   ctx->eps_stored = !(FUSED && !DEBUG && ctx->L.eps_lds);
   if constexpr (FUSED && !DEBUG) {
+    if (ctx->L.deferred && ctx->L.ws) {
+      if (ctx->L.eps_lds)
+        return launch_ws<DYN, JUMPS, DEBUG, FORM, FUSED, FULL, true, true>(ctx, x0, s, sh);
+      return launch_ws<DYN, JUMPS, DEBUG, FORM, FUSED, FULL, false, true>(ctx, x0, s, sh);
+    }
     if (ctx->L.eps_lds) return launch_ws<DYN, JUMPS, DEBUG, FORM, FUSED, FULL, true>(ctx, x0, s, sh);
-  }
-  if constexpr (FUSED && !DEBUG) {
     if (ctx->L.deferred) {
       rollout_kernel<DYN, JUMPS, DEBUG, FORM, FUSED, FULL, true>
           <<<dim3(ctx->L.nwg), dim3(kBlock), 0, s>>>(ctx->p, ctx->b, x0, ctx->b.U, ctx->L.R, sh);

@@ -112,9 +112,15 @@ template <int DYN>
 constexpr size_t ws_eps_lds_bytes(int R) {
   return ws_ring_bytes<DYN, true>() + sizeof(float) * (size_t)R * (kWsSamples + 1);
 }
+// The tile fits when `per_cu` workgroups of the kernel still fit in a
+// compute unit's LDS: one for the fused form (at most 512 workgroups, two
+// per compute unit at most), two for the deferred form, whose thousands of
+// workgroups need the occupancy more than the saved HBM pass (quadrotor
+// K=65536, T=100: the tile on chip, 147 KB of LDS and one workgroup per
+// compute unit, 187.9 us per iteration; in HBM, 75 KB and two, 135.2 us).
 template <int DYN>
-constexpr bool ws_eps_fits(int R) {
-  return ws_eps_lds_bytes<DYN>(R) + kWsStaticLds <= kLdsBytes;
+constexpr bool ws_eps_fits(int R, int per_cu = 1) {
+  return (ws_eps_lds_bytes<DYN>(R) + kWsStaticLds) * per_cu <= kLdsBytes;
 }
 
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FULL, bool EPS_LDS>
@@ -360,9 +366,11 @@ __device__ __forceinline__ double ws_rollout(const DevParams& p, const Consts& c
 // One workgroup (tile wg of nwg) of the wave-specialised rollout, W waves,
 // with its one-iteration epilogue.  U_LDS: U is staged in LDS after the
 // ring and the tile (the single-controller kernels; the batched ones, whose
-// controllers differ in R, read it from global memory).
+// controllers differ in R, read it from global memory).  DEFER: the
+// epilogue's deferred-update form (rollout_epilogue), for more workgroups
+// than one combines.
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, int W, bool FULL = false,
-          bool EPS_LDS = false, bool U_LDS = false>
+          bool EPS_LDS = false, bool U_LDS = false, bool DEFER = false>
 __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffers& b,
                                                 const float* __restrict__ x0,
                                                 const float* U, int R,
@@ -384,17 +392,19 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
   const float* tile = EPS_LDS ? ws_dyn_lds + kRingFloats : b.eps + (size_t)wg * kWsSamples;
   const int tstride = EPS_LDS ? kWsSamples : p.Ks;
   const int k = wg * kWsSamples + (threadIdx.x & 63);
-  rollout_epilogue<kWsSamples, FUSED, 64 * W>(p, b, Sd, (threadIdx.x >> 6) == 0 && k < p.K, R,
-                                              sh, wg, nwg, tile, tstride);
+  const bool holds = (threadIdx.x >> 6) == 0 && k < p.K;  // wavefront 0 holds the costs
+  rollout_epilogue<kWsSamples, FUSED, 64 * W, DEFER>(p, b, Sd, holds, R, sh, wg, nwg, tile,
+                                                     tstride);
 }
 
-template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL, bool EPS_LDS>
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, bool FULL, bool EPS_LDS,
+          bool DEFER = false>
 __global__ __launch_bounds__(64 * WsWaves<DYN>::W) void rollout_ws_kernel(const DevParams p,
                                                                          const Buffers b,
                                                                          const float* __restrict__ x0,
                                                                          const float* U,
                                                                          int R, const ShiftArgs sh) {
-  rollout_ws_tile<DYN, JUMPS, DEBUG, FORM, FUSED, WsWaves<DYN>::W, FULL, EPS_LDS, true>(
+  rollout_ws_tile<DYN, JUMPS, DEBUG, FORM, FUSED, WsWaves<DYN>::W, FULL, EPS_LDS, true, DEFER>(
       p, b, x0, U, R, sh, blockIdx.x, gridDim.x);
 }
 

@@ -1,8 +1,9 @@
-"""The deferred-update form of the one-sample-per-lane rollout, used when a
-controller has more workgroups than the fused epilogue combines: every
+"""The deferred-update form of the rollout, used when a controller has more
+workgroups than the fused epilogue combines (either schedule): every
 workgroup publishes its weighted perturbation sums P[wg][r] of eq. (37), the
 last one to arrive forms the statistics and the rescales, and a separate
-kernel applies eq. (36) from the partials.
+kernel applies eq. (36) from the partials.  The wave-specialised form keeps
+its 64-sample tiles on chip when they fit and then stores no perturbations.
 
   * against the staged form (rollout, then the update kernel over the stored
     perturbations) on the same seeded inputs, over two iterations (arrival
@@ -23,15 +24,24 @@ from paper_1807_06108_amd.controller import Controller
 pytestmark = pytest.mark.gpu
 
 LANE = native.C["MPPI_SCHED_LANE"]
+WS = native.C["MPPI_SCHED_WAVE_SPECIALISED"]
 
-# (preset, K, T): just above the fused limit of 512 workgroups of 256
-# samples with a ragged last workgroup; one row block (R = 48); two row
-# blocks, the second ragged (R = 70); many partials per chunk
+# (preset, K, T, schedule, tile on chip): just above the fused limit of 512
+# workgroups of 256 samples with a ragged last workgroup; one row block
+# (R = 48); two row blocks, the second ragged (R = 70); many partials per
+# chunk; the wave-specialised schedule above 512 workgroups of 64 samples,
+# its tile on chip where two workgroups still fit a compute unit's LDS
+# (T = 20; the quadrotor's T = 12) and in HBM otherwise (T = 600; the
+# quadrotor's T = 100)
 CASES = [
-    ("double_integrator", 131_329, 9),
-    ("cartpole_single", 140_000, 20),
-    ("quadrotor_hover", 140_000, 12),
-    ("cartpole_single", 300_000, 70),
+    ("double_integrator", 131_329, 9, LANE, False),
+    ("cartpole_single", 140_000, 20, LANE, False),
+    ("quadrotor_hover", 140_000, 12, LANE, False),
+    ("cartpole_single", 300_000, 70, LANE, False),
+    ("cartpole_single", 40_001, 20, WS, True),
+    ("quadrotor_hover", 40_000, 12, WS, True),
+    ("cartpole_single", 33_000, 600, WS, False),
+    ("quadrotor_hover", 33_000, 100, WS, False),
 ]
 
 
@@ -43,12 +53,20 @@ def _ulps(a, b):
     return np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)) / unit
 
 
-@pytest.mark.parametrize("preset,K,T", CASES)
-def test_deferred_matches_staged_and_eq36(preset, K, T):
-    cfg = workloads.PRESETS[preset](K=K, T=T, schedule=LANE)
+def _eps_or_none(ctl):
+    try:
+        return ctl.eps.cpu().numpy()
+    except native.MppiError as e:
+        assert e.code == native.C["MPPI_EUNSUPPORTED"]
+        return None
+
+
+@pytest.mark.parametrize("preset,K,T,sched,on_chip", CASES)
+def test_deferred_matches_staged_and_eq36(preset, K, T, sched, on_chip):
+    cfg = workloads.PRESETS[preset](K=K, T=T, schedule=sched)
     U0 = workloads.U0_for(cfg, "random")
     x0 = workloads.x0_for(cfg)
-    print("case", preset, K, T, flush=True)
+    print("case", preset, K, T, sched, flush=True)
     a = Controller(cfg, U0)  # deferred (step)
     b = Controller(cfg, U0)  # staged (rollout + update)
     for it in range(2):
@@ -57,8 +75,11 @@ def test_deferred_matches_staged_and_eq36(preset, K, T):
         b.rollout(x0)
         b.update()
         S, Sb = a.S.cpu().numpy(), b.S.cpu().numpy()
-        eps, epsb = a.eps.cpu().numpy(), b.eps.cpu().numpy()
-        assert np.array_equal(S, Sb) and np.array_equal(eps, epsb)
+        eps, epsb = _eps_or_none(a), b.eps.cpu().numpy()
+        assert np.array_equal(S, Sb)
+        assert (eps is None) == on_chip
+        assert eps is None or np.array_equal(eps, epsb)
+        eps = epsb
         W = a.W.cpu().numpy()
         assert np.allclose(W, b.W.cpu().numpy(), rtol=1e-12, atol=1e-300)
         sa, sb = a.stats(), b.stats()
@@ -79,8 +100,9 @@ def test_deferred_matches_staged_and_eq36(preset, K, T):
         b.set_U(U)
 
 
-def test_deferred_all_nonfinite_leaves_U_unchanged():
-    cfg = workloads.cartpole(K=140_000, T=20, schedule=LANE)
+@pytest.mark.parametrize("K,sched", [(140_000, LANE), (40_001, WS)])
+def test_deferred_all_nonfinite_leaves_U_unchanged(K, sched):
+    cfg = workloads.cartpole(K=K, T=20, schedule=sched)
     U0 = workloads.U0_for(cfg, "random")
     ctl = Controller(cfg, U0)
     ctl.step(np.full(4, np.nan, dtype=np.float32), 1)
