@@ -185,8 +185,9 @@ int mppi_jump_init(const mppi_jump_config* cfg, void* d_workspace, size_t ws_byt
  * draws fresh noise (its own iteration index).  If every S~_k of an
  * iteration is non-finite, that iteration leaves U unchanged and records
  * MPPI_ENONFINITE in the statistics (read with MPPI_ITEM_STATS).
- * With at most 512 rollout workgroups the update of eqs. (36)-(37) runs in
- * the rollout kernel's epilogue (one kernel per iteration).  Beyond that,
+ * With at most 256 rollout workgroups (wave-specialised schedule) or 64
+ * (one sample per lane) the update of eqs. (36)-(37) runs in the rollout
+ * kernel's epilogue (one kernel per iteration).  Beyond that,
  * each workgroup's epilogue publishes its weighted perturbation sums and a
  * second kernel combines them; a context with debug_dump runs the staged
  * pair (mppi_jump_rollout, mppi_jump_update) instead. */
@@ -196,9 +197,8 @@ int mppi_jump_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters, void* s
  * iterations from d_x0 followed by the receding-horizon shift, with u_0 (the
  * control to execute, [m] fp32) written to d_u0_out (device memory; may be
  * NULL).  Equivalent to mppi_jump_step then mppi_jump_shift; when the
- * update is applied inside the rollout kernel (at most 512 rollout
- * workgroups) the shift and the u_0 output are folded into the last
- * iteration's kernel. */
+ * update is applied inside the rollout kernel (see mppi_jump_step) the
+ * shift and the u_0 output are folded into the last iteration's kernel. */
 int mppi_jump_control_step(mppi_jump_ctx* ctx, const float* d_x0, int32_t iters,
                            float* d_u0_out, void* stream);
 
@@ -285,8 +285,8 @@ typedef struct mppi_jump_batch mppi_jump_batch;
 
 /* Device scratch for a batch of n contexts (descriptor table, tile list,
  * u_0 outputs [n][4] fp32, work queue), for a 256-byte aligned base.  Pure host function.
- * EINVAL for NULL/mixed-schedule contexts; EUNSUPPORTED for a context whose
- * update is not fused or that has debug_dump set. */
+ * EINVAL for NULL/mixed-schedule contexts; EUNSUPPORTED for a context with
+ * more than 512 rollout workgroups or with debug_dump set. */
 int mppi_jump_batch_scratch_bytes(mppi_jump_ctx* const* ctxs, int32_t n, size_t* bytes);
 
 /* Build a batch over ctxs[0..n) with states d_x0[i] ([n_i] fp32 device
@@ -373,10 +373,11 @@ int mppi_jump_pool_tick(mppi_jump_pool* pool, const int32_t* ids, const float* s
 /* Put ctx at position `index` of the pool in place of its context, so that
  * a pool of fixed size can hold a changing set of resident controllers (a
  * server admitting a controller in place of one it evicted).  ctx must meet
- * the conditions of the pool's contexts (same rollout schedule; fused
- * update; no debug_dump; diagonal covariance); the position must not be in a
- * tick in flight (EINVAL).  Uploads the position's descriptor on `stream`
- * and synchronises it, so later ticks on any stream see the new context.
+ * the conditions of the pool's contexts (same rollout schedule; at most
+ * 512 rollout workgroups; no debug_dump; diagonal covariance); the position
+ * must not be in a tick in flight (EINVAL).  Uploads the position's
+ * descriptor on `stream` and synchronises it, so later ticks on any stream
+ * see the new context.
  * The caller keeps ctx and its workspace alive while the pool holds it. */
 int mppi_jump_pool_replace(mppi_jump_pool* pool, int32_t index, mppi_jump_ctx* ctx, void* stream);
 

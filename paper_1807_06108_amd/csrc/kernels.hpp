@@ -119,9 +119,19 @@ __device__ __forceinline__ void stage_consts(Consts& cs, const DevParams& p) {
 }
 
 // ------------------------------------------------------------------ epilogue
-// Rollouts with at most this many workgroups apply the update in their own
-// epilogue (one kernel per iteration); larger ones use update_kernel.
+// Most workgroups whose partials one workgroup combines in the fused
+// epilogue (the batched and serving kernels hold controllers up to it).
 constexpr int kFusedMaxWg = 512;
+// A single controller's iteration fuses the update up to these counts and
+// defers it beyond (partial_update_kernel): the last workgroup's combine
+// grows with workgroups x rows, the deferred form costs a second launch.
+// Measured (T=100, us per iteration, fused -> deferred): wave-specialised
+// 128 workgroups 22.8 -> 28.1 (cartpole), 47.8 -> 52.2 (quadrotor); 256:
+// 26.7 -> 32.1, 57.6 -> 58.7; 512: 46.4 -> 39.2, 107.7 -> 75.0.  One sample
+// per lane (256 threads, narrower combine batches) 128 workgroups: 69.8 ->
+// 69.1, 159.0 -> 131.1; 512: 135.2 -> 98.2, 338.6 -> 204.0.
+constexpr int kFusedWgWs = 256;
+constexpr int kFusedWgLane = 64;
 constexpr int kStageRows = 1024;  // partial rows staged in LDS per pass
 
 // Device-scope fences of the last-arrival pattern: the publishing side needs

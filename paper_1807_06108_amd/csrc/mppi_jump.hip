@@ -213,7 +213,7 @@ Layout make_layout(const mppi_jump_config* c, int m, int q) {
   L.part = take((size_t)L.nwg * sizeof(WgPartial));
   L.scale = take((size_t)L.nwg * 8);
   L.upart = take((size_t)L.R * L.nch * 8);
-  L.fused = L.nwg <= kFusedMaxWg;
+  L.fused = L.nwg <= (L.ws ? kFusedWgWs : kFusedWgLane);
   L.deferred = !L.fused && !c->debug_dump;
   const int per_cu = L.fused ? 1 : 2;
   bool fits = false;
@@ -223,7 +223,9 @@ Layout make_layout(const mppi_jump_config* c, int m, int q) {
     default: fits = ws_eps_fits<MPPI_DYN_QUADROTOR>(L.R, per_cu); break;
   }
   L.eps_lds = L.ws && (L.fused || L.deferred) && !c->debug_dump && fits;
-  L.wpart = take(L.fused || L.deferred ? (size_t)L.nwg * L.R * 8 : 0);
+  // the workgroup partials: fused and deferred iterations, and batches
+  // (which fuse up to kFusedMaxWg workgroups per controller)
+  L.wpart = take(L.fused || L.deferred || L.nwg <= kFusedMaxWg ? (size_t)L.nwg * L.R * 8 : 0);
   L.stats = take(sizeof(mppi_jump_stats));
   L.counters = take((size_t)counter_count(L.R) * sizeof(uint32_t));
   L.W = take(K * 8);
@@ -365,7 +367,8 @@ void bind_context(mppi_jump_ctx* ctx, const mppi_jump_config* cfg, int n, int m,
   b.part = reinterpret_cast<WgPartial*>(base + L.part);
   b.scale = reinterpret_cast<double*>(base + L.scale);
   b.upart = reinterpret_cast<double*>(base + L.upart);
-  b.wpart = L.fused || L.deferred ? reinterpret_cast<double*>(base + L.wpart) : nullptr;
+  b.wpart = L.fused || L.deferred || L.nwg <= kFusedMaxWg
+                ? reinterpret_cast<double*>(base + L.wpart) : nullptr;
   b.stats = reinterpret_cast<mppi_jump_stats*>(base + L.stats);
   b.counters = reinterpret_cast<uint32_t*>(base + L.counters);
   ctx->W = reinterpret_cast<double*>(base + L.W);
@@ -883,7 +886,7 @@ int batch_check(mppi_jump_ctx* const* ctxs, int32_t n, BatchLayout& BL, bool& ws
   for (int i = 0; i < n; ++i) {
     const mppi_jump_ctx* c = ctxs[i];
     if (!c) return fail(MPPI_EINVAL, "context %d is NULL", i);
-    if (!c->L.fused)
+    if (c->L.nwg > kFusedMaxWg)
       return fail(MPPI_EUNSUPPORTED, "context %d: K=%d needs more than %d rollout workgroups", i,
                   c->cfg.K, kFusedMaxWg);
     if (c->cfg.debug_dump) return fail(MPPI_EUNSUPPORTED, "context %d has debug_dump set", i);

@@ -26,14 +26,17 @@ pytestmark = pytest.mark.gpu
 LANE = native.C["MPPI_SCHED_LANE"]
 WS = native.C["MPPI_SCHED_WAVE_SPECIALISED"]
 
-# (preset, K, T, schedule, tile on chip): just above the fused limit of 512
-# workgroups of 256 samples with a ragged last workgroup; one row block
-# (R = 48); two row blocks, the second ragged (R = 70); many partials per
-# chunk; the wave-specialised schedule above 512 workgroups of 64 samples,
-# its tile on chip where two workgroups still fit a compute unit's LDS
-# (T = 20; the quadrotor's T = 12) and in HBM otherwise (T = 600; the
-# quadrotor's T = 100)
+# (preset, K, T, schedule, tile on chip): one-sample-per-lane controllers
+# just above the fused limit of 64 workgroups of 256 samples (a ragged last
+# workgroup) and above 512; one row block (R = 48); two row blocks, the
+# second ragged (R = 70); many partials per chunk; the wave-specialised
+# schedule just above its fused limit of 256 workgroups of 64 samples and
+# far above it, its tile on chip where two workgroups still fit a compute
+# unit's LDS (T = 20; the quadrotor's T = 12 and 20) and in HBM otherwise
+# (T = 600; the quadrotor's T = 100)
 CASES = [
+    ("cartpole_single", 16_385, 30, LANE, False),
+    ("quadrotor_hover", 16_385, 20, WS, True),
     ("double_integrator", 131_329, 9, LANE, False),
     ("cartpole_single", 140_000, 20, LANE, False),
     ("quadrotor_hover", 140_000, 12, LANE, False),
