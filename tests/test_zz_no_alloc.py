@@ -42,8 +42,11 @@ def _context_step(cfg, U, x0, iters):
     # the cartpole MPC shape
     (("quadrotor_hover", {}, 1), ("cartpole_mpc", {}, 5)),
     # the cartpole MPC shape, then a ragged smaller one (lane schedule and
-    # the unfused update path: above 512 rollout workgroups)
+    # the deferred update: above 64 rollout workgroups)
     (("cartpole_mpc", {}, 5), ("cartpole_single", dict(K=150_000, T=6), 2)),
+    # the wave-specialised schedule's deferred update (above 256 rollout
+    # workgroups, the tile on chip), cartpole then quadrotor
+    (("cartpole_single", dict(K=40_001, T=30), 2), ("quadrotor_hover", dict(K=20_000, T=25), 1)),
 ])
 def test_static_scratch_matches_the_context_step(first, second):
     for preset, over, iters in (first, second):
