@@ -123,15 +123,15 @@ constexpr bool ws_eps_fits(int R, int per_cu = 1) {
   return (ws_eps_lds_bytes<DYN>(R) + kWsStaticLds) * per_cu <= kLdsBytes;
 }
 
+// The part of a step's production that needs U: the applied controls, the
+// state-free cost and the stores of the draws nz of step t.
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FULL, bool EPS_LDS>
-__device__ __forceinline__ void ws_produce(const DevParams& p, const Consts& cs, const Buffers& b,
-                                           const float* U, float* slot, float* epsl, int t,
-                                           int k, bool active, uint32_t it) {
+__device__ __forceinline__ void ws_finish(const DevParams& p, const Consts& cs, const Buffers& b,
+                                          const Noise<DYN, JUMPS>& nz, const float* U,
+                                          float* slot, float* epsl, int t, int k, bool active) {
   using Md = Model<DYN>;
   using Rg = WsRing<DYN, EPS_LDS>;
   constexpr int M = Md::M, Q = Md::Q;
-  Noise<DYN, JUMPS> nz;
-  draw_noise<DYN, JUMPS, FULL>(nz, p, cs, (uint32_t)t, p.k0 + (uint32_t)k, it);
   float u[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) u[j] = U[t * M + j];
@@ -160,6 +160,15 @@ __device__ __forceinline__ void ws_produce(const DevParams& p, const Consts& cs,
       for (int i = 0; i < Q; ++i) b.dbg_zJ[kt * Q + i] = JUMPS ? nz.z[M + i] : 0.f;
     }
   }
+}
+
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FULL, bool EPS_LDS>
+__device__ __forceinline__ void ws_produce(const DevParams& p, const Consts& cs, const Buffers& b,
+                                           const float* U, float* slot, float* epsl, int t,
+                                           int k, bool active, uint32_t it) {
+  Noise<DYN, JUMPS> nz;
+  draw_noise<DYN, JUMPS, FULL>(nz, p, cs, (uint32_t)t, p.k0 + (uint32_t)k, it);
+  ws_finish<DYN, JUMPS, DEBUG, FORM, FULL, EPS_LDS>(p, cs, b, nz, U, slot, epsl, t, k, active);
 }
 
 template <int DYN>
@@ -259,12 +268,15 @@ __device__ __forceinline__ void ws_consume_chunk(const DevParams& p, const Const
 
 // The rollout of one workgroup (tile wg, W waves) at iteration `it`:
 // returns S~_k of sample wg * 64 + lane in wavefront 0 (also stored to b.S).
-// cs: the staged constants; U: the control sequence (global memory or LDS).
-// With EPS_LDS the perturbation tile is left on chip for the epilogue.
-template <int DYN, bool JUMPS, bool DEBUG, int FORM, int W, bool FULL, bool EPS_LDS>
+// cs: the staged constants; Ug: the control sequence (global memory), which
+// with STAGE_U is copied to Ul (LDS, R floats) and read from there.  With
+// EPS_LDS the perturbation tile is left on chip for the epilogue.
+template <int DYN, bool JUMPS, bool DEBUG, int FORM, int W, bool FULL, bool EPS_LDS,
+          bool STAGE_U = false>
 __device__ __forceinline__ double ws_rollout(const DevParams& p, const Consts& cs,
                                              const Buffers& b, const float* __restrict__ x0,
-                                             const float* U, int wg, uint32_t it) {
+                                             const float* Ug, float* Ul, int R, int wg,
+                                             uint32_t it) {
   using Md = Model<DYN>;
   using Rg = WsRing<DYN, EPS_LDS>;
   constexpr int N = Md::N;
@@ -304,13 +316,33 @@ __device__ __forceinline__ double ws_rollout(const DevParams& p, const Consts& c
   // its own live values and constants, not the union of both.  Both sides
   // pass nch + 1 barriers: chunk c is produced before barrier c and consumed
   // after it.
+  // With STAGE_U the sequence is copied to LDS (Ul) here: its load (the
+  // previous launch wrote it, from another XCD) is issued before the first
+  // chunk's draws, which do not need it, and waited for only after them.
   static_assert(CH % W == 0, "the first chunk splits evenly over the waves");
+  const float* U = STAGE_U ? static_cast<const float*>(Ul) : Ug;
   {
+    constexpr int NS = CH / W;
     const int w = __builtin_amdgcn_readfirstlane(wave);
-    for (int s = w * (CH / W); s < (w + 1) * (CH / W); ++s)
-      if (s < T)
-        ws_produce<DYN, JUMPS, DEBUG, FORM, FULL, EPS_LDS>(p, cs, b, U, ring[0][s], epsl, s, k,
-                                                            active, it);
+    float u_mine = 0.f;
+    if constexpr (STAGE_U) {
+      if ((int)threadIdx.x < R) u_mine = Ug[threadIdx.x];
+    }
+    Noise<DYN, JUMPS> nz[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+      if (w * NS + i < T)
+        draw_noise<DYN, JUMPS, FULL>(nz[i], p, cs, (uint32_t)(w * NS + i), p.k0 + (uint32_t)k, it);
+    if constexpr (STAGE_U) {
+      if ((int)threadIdx.x < R) Ul[threadIdx.x] = u_mine;
+      for (int r = threadIdx.x + 64 * W; r < R; r += 64 * W) Ul[r] = Ug[r];
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < NS; ++i)
+      if (w * NS + i < T)
+        ws_finish<DYN, JUMPS, DEBUG, FORM, FULL, EPS_LDS>(p, cs, b, nz[i], U, ring[0][w * NS + i],
+                                                           epsl, w * NS + i, k, active);
   }
   __syncthreads();
   MPPI_PHASE(b.stats->iteration, wg, (p.K + kWsSamples - 1) / kWsSamples, 7);
@@ -365,8 +397,9 @@ __device__ __forceinline__ double ws_rollout(const DevParams& p, const Consts& c
 
 // One workgroup (tile wg of nwg) of the wave-specialised rollout, W waves,
 // with its one-iteration epilogue.  U_LDS: U is staged in LDS after the
-// ring and the tile (the single-controller kernels; the batched ones, whose
-// controllers differ in R, read it from global memory).  DEFER: the
+// ring and the tile while the first chunk's draws are formed (the
+// single-controller kernels; the batched ones, whose controllers differ in
+// R, read it from global memory).  DEFER: the
 // epilogue's deferred-update form (rollout_epilogue), for more workgroups
 // than one combines.
 template <int DYN, bool JUMPS, bool DEBUG, int FORM, bool FUSED, int W, bool FULL = false,
@@ -380,13 +413,11 @@ __device__ __forceinline__ void rollout_ws_tile(const DevParams& p, const Buffer
   extern __shared__ float ws_dyn_lds[];
   constexpr int kRingFloats = 2 * kWsChunk * WsRing<DYN, EPS_LDS>::NF * 64;
   float* Ul = ws_dyn_lds + kRingFloats + (EPS_LDS ? (size_t)R * kWsSamples : 0);
-  if constexpr (U_LDS)
-    for (int r = threadIdx.x; r < R; r += 64 * W) Ul[r] = U[r];
   __shared__ Consts cs;
-  stage_consts(cs, p);  // its barrier also publishes Ul
+  stage_consts(cs, p);
   const uint32_t it = (uint32_t)b.stats->iteration;
-  const double Sd = ws_rollout<DYN, JUMPS, DEBUG, FORM, W, FULL, EPS_LDS>(
-      p, cs, b, x0, U_LDS ? static_cast<const float*>(Ul) : U, wg, it);
+  const double Sd = ws_rollout<DYN, JUMPS, DEBUG, FORM, W, FULL, EPS_LDS, U_LDS>(p, cs, b, x0, U,
+                                                                                Ul, R, wg, it);
   // the epilogue's weighted sums read the tile on chip, or the workgroup's
   // columns of the HBM perturbations
   const float* tile = EPS_LDS ? ws_dyn_lds + kRingFloats : b.eps + (size_t)wg * kWsSamples;
