@@ -272,21 +272,22 @@ const char* mppi_jump_strerror(int code);
 const char* mppi_jump_last_error(void);
 
 /* ---- batched form: many controllers advanced by one launch ----
- * A batch groups contexts created with the same rollout schedule (each with
- * at most 512 rollout workgroups and without debug_dump) and advances all of
- * them by one iteration per kernel launch: one grid over every controller's
- * tiles, longest first, driven by a device table of their parameters and
- * buffers.  Each controller keeps its own workspace, iteration counter and
- * noise stream, so a batched iteration gives exactly the results of
- * mppi_jump_step / mppi_jump_control_step on that controller alone.  The
- * tables are built once at creation; step calls take no pointers and can be
- * captured in a HIP graph and replayed. */
+ * A batch groups contexts created with the same rollout schedule (each
+ * whose own iteration is fused, see mppi_jump_step, and without debug_dump)
+ * and advances all of them by one iteration per kernel launch: one grid
+ * over every controller's tiles, longest first, driven by a device table of
+ * their parameters and buffers.  Each controller keeps its own workspace,
+ * iteration counter and noise stream, so a batched iteration gives exactly
+ * the results of mppi_jump_step / mppi_jump_control_step on that controller
+ * alone.  The tables are built once at creation; step calls take no
+ * pointers and can be captured in a HIP graph and replayed. */
 typedef struct mppi_jump_batch mppi_jump_batch;
 
 /* Device scratch for a batch of n contexts (descriptor table, tile list,
  * u_0 outputs [n][4] fp32, work queue), for a 256-byte aligned base.  Pure host function.
- * EINVAL for NULL/mixed-schedule contexts; EUNSUPPORTED for a context with
- * more than 512 rollout workgroups or with debug_dump set. */
+ * EINVAL for NULL/mixed-schedule contexts; EUNSUPPORTED for a context whose
+ * own iteration is not fused (more rollout workgroups than mppi_jump_step
+ * fuses) or that has debug_dump set. */
 int mppi_jump_batch_scratch_bytes(mppi_jump_ctx* const* ctxs, int32_t n, size_t* bytes);
 
 /* Build a batch over ctxs[0..n) with states d_x0[i] ([n_i] fp32 device
@@ -373,8 +374,8 @@ int mppi_jump_pool_tick(mppi_jump_pool* pool, const int32_t* ids, const float* s
 /* Put ctx at position `index` of the pool in place of its context, so that
  * a pool of fixed size can hold a changing set of resident controllers (a
  * server admitting a controller in place of one it evicted).  ctx must meet
- * the conditions of the pool's contexts (same rollout schedule; at most
- * 512 rollout workgroups; no debug_dump; diagonal covariance); the position
+ * the conditions of the pool's contexts (same rollout schedule; a fused
+ * iteration; no debug_dump; diagonal covariance); the position
  * must not be in a tick in flight (EINVAL).  Uploads the position's
  * descriptor on `stream` and synchronises it, so later ticks on any stream
  * see the new context.

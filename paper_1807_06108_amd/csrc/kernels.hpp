@@ -120,7 +120,7 @@ __device__ __forceinline__ void stage_consts(Consts& cs, const DevParams& p) {
 
 // ------------------------------------------------------------------ epilogue
 // Most workgroups whose partials one workgroup combines in the fused
-// epilogue (the batched and serving kernels hold controllers up to it).
+// epilogue (the size of its rescale table in LDS).
 constexpr int kFusedMaxWg = 512;
 // A single controller's iteration fuses the update up to these counts and
 // defers it beyond (partial_update_kernel): the last workgroup's combine
@@ -130,8 +130,11 @@ constexpr int kFusedMaxWg = 512;
 // 26.7 -> 32.1, 57.6 -> 58.7; 512: 46.4 -> 39.2, 107.7 -> 75.0.  One sample
 // per lane (256 threads, narrower combine batches) 128 workgroups: 69.8 ->
 // 69.1, 159.0 -> 131.1; 512: 135.2 -> 98.2, 338.6 -> 204.0.
+// Batches take only controllers within these limits, so a batched
+// iteration runs the same epilogue as the controller's own.
 constexpr int kFusedWgWs = 256;
 constexpr int kFusedWgLane = 64;
+static_assert(kFusedWgWs <= kFusedMaxWg && kFusedWgLane <= kFusedMaxWg, "fused limits");
 constexpr int kStageRows = 1024;  // partial rows staged in LDS per pass
 
 // Device-scope fences of the last-arrival pattern: the publishing side needs

@@ -223,9 +223,7 @@ Layout make_layout(const mppi_jump_config* c, int m, int q) {
     default: fits = ws_eps_fits<MPPI_DYN_QUADROTOR>(L.R, per_cu); break;
   }
   L.eps_lds = L.ws && (L.fused || L.deferred) && !c->debug_dump && fits;
-  // the workgroup partials: fused and deferred iterations, and batches
-  // (which fuse up to kFusedMaxWg workgroups per controller)
-  L.wpart = take(L.fused || L.deferred || L.nwg <= kFusedMaxWg ? (size_t)L.nwg * L.R * 8 : 0);
+  L.wpart = take(L.fused || L.deferred ? (size_t)L.nwg * L.R * 8 : 0);
   L.stats = take(sizeof(mppi_jump_stats));
   L.counters = take((size_t)counter_count(L.R) * sizeof(uint32_t));
   L.W = take(K * 8);
@@ -367,8 +365,7 @@ void bind_context(mppi_jump_ctx* ctx, const mppi_jump_config* cfg, int n, int m,
   b.part = reinterpret_cast<WgPartial*>(base + L.part);
   b.scale = reinterpret_cast<double*>(base + L.scale);
   b.upart = reinterpret_cast<double*>(base + L.upart);
-  b.wpart = L.fused || L.deferred || L.nwg <= kFusedMaxWg
-                ? reinterpret_cast<double*>(base + L.wpart) : nullptr;
+  b.wpart = L.fused || L.deferred ? reinterpret_cast<double*>(base + L.wpart) : nullptr;
   b.stats = reinterpret_cast<mppi_jump_stats*>(base + L.stats);
   b.counters = reinterpret_cast<uint32_t*>(base + L.counters);
   ctx->W = reinterpret_cast<double*>(base + L.W);
@@ -886,9 +883,11 @@ int batch_check(mppi_jump_ctx* const* ctxs, int32_t n, BatchLayout& BL, bool& ws
   for (int i = 0; i < n; ++i) {
     const mppi_jump_ctx* c = ctxs[i];
     if (!c) return fail(MPPI_EINVAL, "context %d is NULL", i);
-    if (c->L.nwg > kFusedMaxWg)
+    // only controllers whose own iteration is fused: a batched iteration
+    // then runs the same epilogue and gives the same results bitwise
+    if (!c->L.fused)
       return fail(MPPI_EUNSUPPORTED, "context %d: K=%d needs more than %d rollout workgroups", i,
-                  c->cfg.K, kFusedMaxWg);
+                  c->cfg.K, c->L.ws ? kFusedWgWs : kFusedWgLane);
     if (c->cfg.debug_dump) return fail(MPPI_EUNSUPPORTED, "context %d has debug_dump set", i);
     if (c->p.full) return fail(MPPI_EUNSUPPORTED, "context %d has a full noise covariance", i);
     if (i == 0) ws = c->L.ws;

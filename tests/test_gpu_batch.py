@@ -118,10 +118,15 @@ def test_batch_error_paths():
     with pytest.raises(native.MppiError) as e:
         Batch([lane, dbg], [x, x])
     assert e.value.code == native.C["MPPI_EUNSUPPORTED"]
-    big = Controller(workloads.cartpole(K=200_000, T=5, schedule=LANE))
-    with pytest.raises(native.MppiError) as e:
-        Batch([big], [x])
-    assert e.value.code == native.C["MPPI_EUNSUPPORTED"]
+    # controllers whose own iteration is not fused: far above and just above
+    # the limits (64 lane workgroups, 256 wave-specialised)
+    for cfg in (workloads.cartpole(K=200_000, T=5, schedule=LANE),
+                workloads.cartpole(K=16_385, T=5, schedule=LANE),
+                workloads.cartpole(K=16_385, T=5, schedule=WS)):
+        big = Controller(cfg)
+        with pytest.raises(native.MppiError) as e:
+            Batch([big], [x])
+        assert e.value.code == native.C["MPPI_EUNSUPPORTED"]
 
 
 @pytest.mark.parametrize("launch", [GRID, PERSISTENT])
