@@ -68,8 +68,8 @@ struct Buffers {
   double* E;          // [K] exp(-(S_k - rho_wg)/lambda)
   WgPartial* part;    // [ceil(K/256)]
   double* scale;      // [ceil(K/256)] exp(-(rho_wg - rho)/lambda)
-  double* upart;      // [T*m][nch]   chunk partials of update_kernel
-  double* wpart;      // [nwg][T*m]   workgroup partials of the fused epilogue
+  double* upart;      // [T*m][nch]   chunk partials of update_kernel, partial_update_kernel
+  double* wpart;      // [nwg][T*m]   workgroup partials of the fused and deferred epilogues
   mppi_jump_stats* stats;
   uint32_t* counters; // [counter_count(T*m)] arrival counters
   float* dbg_zD;      // [K][T][m]

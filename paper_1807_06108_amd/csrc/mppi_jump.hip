@@ -179,11 +179,11 @@ struct Layout {
   int R, Ks, nwg, nch, chunk;
   bool ws;     // wave-specialised schedule (64 samples per workgroup)
   int spw;     // samples per rollout workgroup
-  bool fused;
-  // rollouts with more workgroups than the fused form combines: tile sums
-  // published, update by partial_update_kernel
+  bool fused;     // the update in the rollout's epilogue (kFusedWgWs / kFusedWgLane)
+  // beyond that (no debug dumps): tile sums published, the update by
+  // partial_update_kernel
   bool deferred;
-  bool eps_lds;  // fused wave-specialised iterations keep the perturbations on chip
+  bool eps_lds;  // wave-specialised iterations keep the perturbations on chip
   size_t U, eps, S, E, part, scale, upart, wpart, stats, counters, W, zD, N, zJ, total;
 };
 
