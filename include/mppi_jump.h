@@ -78,11 +78,15 @@ extern "C" {
  * one sample per lane, 256 samples per workgroup; or wave-specialised, 64
  * samples per workgroup of 8 wavefronts (7 draw noise, 1 runs the state
  * recursion), for latency when K does not fill the GPU.  AUTO picks
- * wave-specialised for K <= MPPI_JUMP_WS_MAX_K. */
+ * wave-specialised for K <= MPPI_JUMP_WS_MAX_K, or K <=
+ * MPPI_JUMP_WS_MAX_K_MULTI for a model with several control channels (the
+ * quadrotor: its heavier draws make the one-sample-per-lane schedule the
+ * faster one sooner). */
 #define MPPI_SCHED_AUTO 0
 #define MPPI_SCHED_LANE 1
 #define MPPI_SCHED_WAVE_SPECIALISED 2
 #define MPPI_JUMP_WS_MAX_K 131072
+#define MPPI_JUMP_WS_MAX_K_MULTI 98304
 
 /* items of mppi_jump_get / mppi_jump_set */
 #define MPPI_ITEM_U 0        /* float [T][m]                        get, set */

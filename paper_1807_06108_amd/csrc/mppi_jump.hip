@@ -191,8 +191,12 @@ Layout make_layout(const mppi_jump_config* c, int m, int q) {
   Layout L{};
   const size_t K = (size_t)c->K, T = (size_t)c->T;
   L.R = (int)(T * m);
+  // AUTO: the wave-specialised schedule up to the measured crossover (T=100,
+  // us per iteration, lane against wave-specialised: quadrotor K=98304
+  // 189.1 / 182.4, K=114688 193.5 / 216.4; cartpole K=131072 99.0 / 92.9)
+  const int ws_max_k = m > 1 ? MPPI_JUMP_WS_MAX_K_MULTI : MPPI_JUMP_WS_MAX_K;
   L.ws = c->schedule == MPPI_SCHED_WAVE_SPECIALISED ||
-         (c->schedule == MPPI_SCHED_AUTO && c->K <= MPPI_JUMP_WS_MAX_K);
+         (c->schedule == MPPI_SCHED_AUTO && c->K <= ws_max_k);
   L.spw = L.ws ? kWsSamples : kBlock;
   L.Ks = (int)align_up(K, kBlock);  // rows padded to whole rollout workgroups
   L.nwg = (int)((K + L.spw - 1) / L.spw);

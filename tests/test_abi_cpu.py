@@ -82,6 +82,22 @@ def test_workspace_bytes_scales_with_the_problem():
     assert dbg >= lane + 256 * 50 * 12
 
 
+def test_auto_schedule_limits():
+    # AUTO takes the wave-specialised schedule up to MPPI_JUMP_WS_MAX_K
+    # samples, MPPI_JUMP_WS_MAX_K_MULTI for the multi-channel quadrotor; the
+    # two schedules' workspaces differ (per-workgroup partials of 64 or 256
+    # samples), which shows the choice
+    LANE, WS = native.C["MPPI_SCHED_LANE"], native.C["MPPI_SCHED_WAVE_SPECIALISED"]
+    for mk, limit in ((workloads.cartpole, native.C["MPPI_JUMP_WS_MAX_K"]),
+                      (workloads.quadrotor, native.C["MPPI_JUMP_WS_MAX_K_MULTI"])):
+        for K, sched in ((limit, WS), (limit + 1, LANE)):
+            auto = native.workspace_bytes(mk(K=K, T=20))
+            assert auto == native.workspace_bytes(mk(K=K, T=20, schedule=sched)), (K, sched)
+            other = LANE if sched == WS else WS
+            assert auto != native.workspace_bytes(mk(K=K, T=20, schedule=other)), (K, sched)
+    assert native.C["MPPI_JUMP_WS_MAX_K_MULTI"] < native.C["MPPI_JUMP_WS_MAX_K"]
+
+
 BAD = [
     ("dynamics", 3), ("K", 0), ("K", 2**24 + 1), ("T", 0), ("T", 4097), ("dt", 0.0),
     ("dt", float("nan")), ("lambda", 0.0), ("lambda", -1.0), ("c", 0.0), ("nu", -0.1),
