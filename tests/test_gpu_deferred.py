@@ -116,3 +116,36 @@ def test_deferred_all_nonfinite_leaves_U_unchanged(K, sched):
     ctl.step(workloads.x0_for(cfg), 1)
     st = ctl.stats()
     assert st["status"] == 0 and st["iteration"] == 2 and st["n_finite"] == cfg["K"]
+
+
+# the kernel variants of the deferred form: the quadrotor's full noise
+# covariance (Sigma_D = L L^T), the SO cost form, no jumps; each just above
+# its schedule's fused limit, deferred step against the staged pair
+VARIANTS = [
+    ("quadrotor_hover", dict(full_sigma=1, sigma_L=workloads.random_cholesky(4, 0.6, seed=12))),
+    ("quadrotor_hover", dict(cost_form=1)),
+    ("cartpole_single", dict(cost_form=1)),
+    ("cartpole_single", dict(nu=0.0)),
+    ("double_integrator", dict(count_law=1, nu=5.0)),
+]
+
+
+@pytest.mark.parametrize("sched,K", [(LANE, 16_385), (WS, 16_448)])
+@pytest.mark.parametrize("preset,over", VARIANTS)
+def test_deferred_variants_match_staged(preset, over, sched, K):
+    cfg = workloads.PRESETS[preset](K=K, T=12, schedule=sched, **over)
+    U0 = workloads.U0_for(cfg, "random")
+    x0 = workloads.x0_for(cfg)
+    print("case", preset, sorted(over), sched, K, flush=True)
+    a = Controller(cfg, U0)
+    b = Controller(cfg, U0)
+    a.step(x0, 1)
+    b.rollout(x0)
+    b.update()
+    assert np.array_equal(a.S.cpu().numpy(), b.S.cpu().numpy())
+    eps = _eps_or_none(a)
+    assert eps is None or np.array_equal(eps, b.eps.cpu().numpy())
+    sa, sb = a.stats(), b.stats()
+    assert sa["iteration"] == sb["iteration"] == 1 and sa["rho"] == sb["rho"]
+    assert sa["n_finite"] == sb["n_finite"] and abs(sa["eta"] - sb["eta"]) <= 1e-12 * sb["eta"]
+    np.testing.assert_array_max_ulp(a.U.cpu().numpy(), b.U.cpu().numpy(), maxulp=1)
